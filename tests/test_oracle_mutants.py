@@ -1,0 +1,185 @@
+"""Planted mistakes: each pin must catch a plausible error in the checker.
+
+A copy of the FP64 checker's source is altered in one place (a dropped term,
+a wrong sign or index, a transposed operand, a wrong constant), compiled into
+a temporary directory on the CPU, and run against the pin that should notice.
+The unaltered checker passes the same pins in ``test_oracle_pins.py``.
+"""
+import subprocess
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import analytic as A
+import oracle
+from paper_2301_12010_amd import inputs
+
+SRC = Path(oracle.__file__).resolve().parent / "swe_oracle.c"
+F64 = np.float64
+
+
+def _compile(tmp: Path, old: str, new: str):
+    text = SRC.read_text()
+    assert text.count(old) == 1, f"mutation anchor not unique: {old!r}"
+    src = tmp / "mutant.c"
+    src.write_text(text.replace(old, new))
+    so = tmp / "libmutant.so"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC",
+                    "-shared", "-o", str(so), str(src), "-lm"], check=True)
+    return oracle.load(so)
+
+
+# --- detectors: return True when the pin flags the library -----------------
+
+def lake_flags(L):
+    sc = inputs.lake_at_rest(nx=32, ny=28, dtype=F64)
+    o = oracle.Oracle.from_scenario(sc, L=L)
+    o.step(100)
+    h, hu, hv = o.state()
+    err = max(np.abs(hu).max(), np.abs(hv).max(), np.abs(h + sc.b - 1.7).max())
+    return not err <= 1e-10
+
+
+def dam_flags(L):
+    sc = inputs.dam_break(nx=128, ny=3)
+    o = oracle.Oracle.from_scenario(sc, L=L)
+    while o.scalars()["t"] < 8.0:
+        if o.step(1) != 0:
+            return True
+    h = o.state()[0][1]
+    x = np.arange(128) + 0.5
+    return not A.rel_l2(h, A.dam_break_h(x, o.scalars()["t"], 2.0, 1.0, 64.0)) < 2e-2
+
+
+def mirror_flags(L):
+    sc = inputs.random_wet(21, 13, seed=9, dry_fraction=0.05)
+    o1 = oracle.Oracle.from_scenario(sc, L=L)
+    o2 = oracle.Oracle.from_scenario(inputs.mirror_x(sc), L=L)
+    o1.step(5)
+    o2.step(5)
+    h, hu, _ = o1.state()
+    hm, hum, _ = o2.state()
+    return not (np.array_equal(hm, h[:, ::-1]) and np.array_equal(hum, -hu[:, ::-1]))
+
+
+def transpose_flags(L):
+    sc = inputs.random_wet(21, 13, seed=4, dry_fraction=0.05)
+    o1 = oracle.Oracle.from_scenario(sc, L=L)
+    o2 = oracle.Oracle.from_scenario(inputs.transpose(sc), L=L)
+    o1.step(5)
+    o2.step(5)
+    h, hu, hv = o1.state()
+    hT, huT, hvT = o2.state()
+    return not (np.array_equal(hT, h.T) and np.array_equal(huT, hv.T))
+
+
+def order_flags(L):
+    nx = 80
+    x = np.arange(nx) + 0.5
+    H = np.broadcast_to(1.0 + 0.1 * np.exp(-((x - 40.0) / 6.0) ** 2), (3, nx)).copy()
+    z = np.zeros((3, nx))
+
+    def run(dt, T=4.0):
+        o = oracle.Oracle(inputs.Params(nx, 3, 1.0, 1.0, cfl=0.0, dt_fixed=dt), z, z, H, z, z, L=L)
+        o.step(int(round(T / dt)))
+        return o.state()[0][1]
+
+    ref = run(0.00625)
+    e = [np.abs(run(dt) - ref).max() for dt in (0.2, 0.1)]
+    return not 6.0 < e[0] / e[1] < 10.0
+
+
+def slope_flags(L):
+    o = oracle.Oracle.from_scenario(inputs.steady_slope(dtype=F64), L=L)
+    return not max(np.abs(a).max() for a in o.rhs()) < 1e-12
+
+
+def wall_flags(L):
+    o = oracle.Oracle.from_scenario(inputs.dam_break(nx=40, ny=3, x0=10.0), L=L)
+    m0 = o.scalars()["mass"]
+    o.step(800)
+    return not abs(o.scalars()["mass"] - m0) <= 1e-13 * m0
+
+
+def clamp_flags(L):
+    o = oracle.Oracle.from_scenario(inputs.parabolic_bowl(nx=300, ny=3, dx=2.0, dtype=F64), L=L)
+    m0 = o.scalars()["mass"]
+    o.step(300)
+    s = o.scalars()
+    return not abs(s["mass"] - m0 - s["clamp_mass"]) <= 1e-12 * m0
+
+
+def poly_flags(L):
+    x, dx = 0.37, 0.1
+    for deg in range(6):
+        f = lambda s: s ** deg
+        fp = oracle.weno5([f(x + k * dx) for k in (-2, -1, 0, 1, 2)], 1e30, L=L)[0]
+        fm = oracle.weno5([f(x + k * dx) for k in (-3, -2, -1, 0, 1)], 1e30, L=L)[0]
+        exact = deg * x ** (deg - 1) if deg else 0.0
+        if abs((fp - fm) / dx - exact) > 1e-11 * max(1.0, abs(exact)):
+            return True
+    return False
+
+
+def fifth_order_flags(L):
+    def err(dx):
+        fp = oracle.weno5([np.sin(0.4 + k * dx) for k in (-2, -1, 0, 1, 2)], 1e-6, L=L)[0]
+        fm = oracle.weno5([np.sin(0.4 + k * dx) for k in (-3, -2, -1, 0, 1)], 1e-6, L=L)[0]
+        return abs((fp - fm) / dx - np.cos(0.4))
+    return not err(0.2) / err(0.1) > 20.0
+
+
+def step_weights_flags(L):
+    _, w = oracle.weno5([0.0, 0.0, 0.0, 1.0, 1.0], L=L)
+    return not (w[0] > 1 - 1e-10 and w[1] + w[2] < 1e-10)
+
+
+MUTANTS = [
+    # (id, anchor, replacement, detector)
+    ("surface_viscosity_on_h", "U[0] = h + b;", "U[0] = h;", lake_flags),
+    ("bed_weights_from_mass", "const int mb = dir == 0 ? 1 : 2;", "const int mb = 0;", lake_flags),
+    ("bed_y_sign", "c->bedy[o] = -g * eta * db[j] / c->p.dy;",
+     "c->bedy[o] = g * eta * db[j] / c->p.dy;", lake_flags),
+    ("pressure_drops_bed", "const double pres = 0.5 * c->p.g * (h * h - b * b);",
+     "const double pres = 0.5 * c->p.g * h * h;", lake_flags),
+    ("minus_stencil_not_mirrored", "vm[s] = Fm[(k + 3 - s + HALO) * 3 + m];",
+     "vm[s] = Fm[(k - 2 + s + HALO) * 3 + m];", dam_flags),
+    ("advective_flux_dropped", "F[1] = hu * u + pres;", "F[1] = pres;", dam_flags),
+    ("split_sign", "Fm[(k + HALO) * 3 + m] = 0.5 * (F[m] - alpha * U[m]);",
+     "Fm[(k + HALO) * 3 + m] = 0.5 * (F[m] + alpha * U[m]);", dam_flags),
+    ("rk_stage2_weights", "combine(c, 0.75, 0.25,", "combine(c, 0.5, 0.5,", order_flags),
+    ("rk_stage3_weights", "combine(c, 1.0 / 3.0, 2.0 / 3.0,", "combine(c, 0.5, 0.5,", order_flags),
+    ("friction_exponent", "pow(h[e], 7.0 / 3.0)", "pow(h[e], 4.0 / 3.0)", slope_flags),
+    ("bed_ghost_not_linear", "b[IX(c, -1 - k, j)] = b[IX(c, 0, j)] + (k + 1) * (b[IX(c, 0, j)] - b[IX(c, 1, j)]);",
+     "b[IX(c, -1 - k, j)] = b[IX(c, 0, j)];", slope_flags),
+    ("wall_normal_momentum_even", "h[g] = h[s]; hu[g] = -hu[s]; hv[g] = hv[s];\n            } else {\n                h[g] = c->ghost[WEST]",
+     "h[g] = h[s]; hu[g] = hu[s]; hv[g] = hv[s];\n            } else {\n                h[g] = c->ghost[WEST]", wall_flags),
+    ("clamp_weight_stage1", "combine(c, 0.0, 1.0, 1.0 / 6.0, dt, c->h, c->hu, c->hv, c->h, c->hu, c->hv,\n                c->h1",
+     "combine(c, 0.0, 1.0, 1.0, dt, c->h, c->hu, c->hv, c->h, c->hu, c->hv,\n                c->h1", clamp_flags),
+    ("linear_weights", "static const double d[3] = {0.1, 0.6, 0.3};",
+     "static const double d[3] = {0.2, 0.5, 0.3};", poly_flags),
+    ("candidate_q2", "q[2] = (2.0 * v[2] + 5.0 * v[3] - v[4]) / 6.0;",
+     "q[2] = (2.0 * v[2] + 5.0 * v[3] + v[4]) / 6.0;", poly_flags),
+    ("beta1_not_squared", "beta[1] = 13.0 / 12.0 * s1 * s1 + 0.25 * t1 * t1;",
+     "beta[1] = 13.0 / 12.0 * s1 + 0.25 * t1 * t1;", fifth_order_flags),
+    ("beta0_one_sided_term", "t0 = v[0] - 4.0 * v[1] + 3.0 * v[2];",
+     "t0 = v[0] - 4.0 * v[1] + 2.0 * v[2];", fifth_order_flags),
+    ("epsilon_inside_square_missing", "a[k] = d[k] / ((eps + beta[k]) * (eps + beta[k]));",
+     "a[k] = d[k] / (eps + beta[k]);", step_weights_flags),
+    ("alpha_y_uses_u", "const double sx = fabs(u) + cel, sy = fabs(v) + cel;",
+     "const double sx = fabs(u) + cel, sy = fabs(u) + cel;", transpose_flags),
+    ("bed_source_x_index", "dbh[k] = bhat[k + 1] - bhat[k];", "dbh[k] = bhat[k + 1] - bhat[k + 1];", lake_flags),
+]
+
+
+@pytest.mark.parametrize("mid,old,new,detector", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pin_catches_planted_mistake(tmp_path, mid, old, new, detector):
+    L = _compile(tmp_path, old, new)
+    assert detector(L), f"planted mistake {mid} went unnoticed"
+
+
+def test_detectors_pass_on_the_real_checker():
+    L = oracle.lib()
+    for det in {m[3] for m in MUTANTS}:
+        assert not det(L), det.__name__

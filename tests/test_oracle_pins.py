@@ -1,0 +1,303 @@
+"""Pins of the FP64 checker against what the paper and the mathematics fix.
+
+Each test names the passage it follows.  None of them re-types the checker's
+formulas: they compare it with closed forms (Stoker dam break, Thacker bowl,
+Manning uniform flow, lake at rest), polynomial exactness of the WENO5
+reconstruction, conservation, and exact symmetries of the discrete operator.
+"""
+import numpy as np
+import pytest
+
+import analytic as A
+import oracle
+from paper_2301_12010_amd import inputs
+
+F64 = np.float64
+
+
+def run_to(o, t_end):
+    while o.scalars()["t"] < t_end:
+        assert o.step(1) == 0
+    return o.scalars()
+
+
+# ---------------------------------------------------------------------------
+# WENO5 reconstruction (Methods, WENO paragraph; Jiang & Shu)
+# ---------------------------------------------------------------------------
+
+def _fd_derivative(f, x, dx, eps):
+    """(fhat_{i+1/2} - fhat_{i-1/2})/dx with fhat = R+(f_{i-2..i+2})."""
+    fp = oracle.weno5([f(x + k * dx) for k in (-2, -1, 0, 1, 2)], eps)[0]
+    fm = oracle.weno5([f(x + k * dx) for k in (-3, -2, -1, 0, 1)], eps)[0]
+    return (fp - fm) / dx
+
+
+@pytest.mark.parametrize("deg", [0, 1, 2, 3, 4, 5])
+def test_weno5_linear_weights_exact_to_degree_5(deg):
+    # with the linear weights the flux difference is the 6-point upwind
+    # derivative, exact for polynomials of degree <= 5
+    x, dx = 0.37, 0.1
+    f = lambda s: s ** deg
+    d = _fd_derivative(f, x, dx, eps=1e30)
+    exact = deg * x ** (deg - 1) if deg else 0.0
+    assert abs(d - exact) <= 1e-11 * max(1.0, abs(exact))
+
+
+def test_weno5_linear_weights_not_exact_at_degree_6():
+    x, dx = 0.37, 0.1
+    d = _fd_derivative(lambda s: s ** 6, x, dx, eps=1e30)
+    assert abs(d - 6 * x ** 5) > 1e-6
+
+
+def test_weno5_fifth_order_with_nonlinear_weights():
+    # smooth data, default epsilon: error falls like dx^5
+    f = lambda s: np.sin(s)
+    errs = [abs(_fd_derivative(f, 0.4, dx, 1e-6) - np.cos(0.4)) for dx in (0.2, 0.1)]
+    assert errs[0] / errs[1] > 20.0
+
+
+def test_weno5_odd_symmetry_bitwise():
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        v = rng.standard_normal(5) * rng.uniform(1e-3, 1e3)
+        r, w = oracle.weno5(v)
+        rn, wn = oracle.weno5(-v)
+        assert rn == -r
+        assert np.array_equal(w, wn)
+
+
+def test_weno5_weights_on_step_and_normalisation():
+    # a jump between v[2] and v[3]: only the left stencil is smooth
+    r, w = oracle.weno5([0.0, 0.0, 0.0, 1.0, 1.0])
+    assert w[0] > 1 - 1e-10 and w[1] + w[2] < 1e-10
+    assert abs(r) < 1e-10
+    rng = np.random.default_rng(3)
+    for _ in range(100):
+        _, w = oracle.weno5(rng.standard_normal(5))
+        assert abs(w.sum() - 1.0) <= 4 * np.finfo(float).eps
+
+
+# ---------------------------------------------------------------------------
+# Wet dam break (Section 2.1)
+# ---------------------------------------------------------------------------
+
+def test_stoker_closed_form_is_consistent():
+    # the quartic's root must satisfy the Rankine-Hugoniot conditions of the
+    # right-moving bore with the rarefaction's Riemann invariant
+    g, hl, hr = 9.81, 2.0, 1.0
+    cm = A.stoker_cm(hl, hr)
+    hm = cm * cm / g
+    um = 2.0 * (np.sqrt(g * hl) - cm)
+    _, _, x3, _ = A.dam_break_fronts(1.0, hl, hr, 0.0)
+    s = x3  # shock speed
+    assert abs(s * (hm - hr) - hm * um) < 1e-10  # mass
+    mom = s * hm * um - (hm * um * um + 0.5 * g * (hm * hm - hr * hr))
+    assert abs(mom) < 1e-9  # momentum
+    assert np.sqrt(g * hr) < cm < np.sqrt(g * hl)
+
+
+def test_dam_break_config_against_stoker():
+    sc = inputs.dam_break()  # 128 x 64, dx = 1, CFL 0.4, 200 steps, reflective walls
+    o = oracle.Oracle.from_scenario(sc)
+    assert o.step(sc.nsteps) == 0
+    s = o.scalars()
+    h, hu, hv = o.state()
+    # CFL 0.4 with dt = cfl/(ax/dx + ay/dy): 200 steps end before any wave
+    # reaches a wall
+    assert 8.0 < s["t"] < 9.0
+    x = (np.arange(sc.params.nx) + 0.5) * sc.params.dx
+    ha = A.dam_break_h(x, s["t"], 2.0, 1.0, 64.0)
+    x1, x2, x3, _ = A.dam_break_fronts(s["t"], 2.0, 1.0, 64.0)
+    assert 0 < x1 and x3 < 128
+    for row in (0, 31, 63):
+        assert A.rel_l2(h[row], ha) < 2.0e-2
+        assert A.rel_linf(h[row], ha) < 0.2
+        away = (np.abs(x - x1) > 3) & (np.abs(x - x2) > 3) & (np.abs(x - x3) > 3)
+        assert A.rel_l2(h[row][away], ha[away]) < 2.5e-3
+    # a y-uniform problem stays y-uniform bitwise and hv stays exactly zero
+    assert np.array_equal(h, np.broadcast_to(h[0], h.shape))
+    assert np.all(hv == 0.0)
+
+
+def test_dam_break_converges_first_order_in_l1():
+    errs = []
+    for nx, dx in [(128, 1.0), (256, 0.5), (512, 0.25)]:
+        o = oracle.Oracle.from_scenario(inputs.dam_break(nx=nx, ny=3, dx=dx))
+        s = run_to(o, 8.0)
+        h = o.state()[0][1]
+        x = (np.arange(nx) + 0.5) * dx
+        errs.append(np.mean(np.abs(h - A.dam_break_h(x, s["t"], 2.0, 1.0, 64.0))))
+    assert errs[0] / errs[1] > 1.7 and errs[1] / errs[2] > 1.7
+
+
+def test_reflective_wall_mass_flux_is_zero():
+    # a wave hitting the walls: mass is conserved to rounding of the sum
+    sc = inputs.dam_break(nx=40, ny=3, dx=1.0, x0=10.0)
+    o = oracle.Oracle.from_scenario(sc)
+    m0 = o.scalars()["mass"]
+    o.step(800)
+    s = o.scalars()
+    assert s["t"] > 30.0  # several wall reflections
+    assert abs(s["mass"] - m0) <= 1e-13 * m0
+
+
+# ---------------------------------------------------------------------------
+# Planar parabolic bowl (Section 2.2): wet/dry fronts
+# ---------------------------------------------------------------------------
+
+def test_parabolic_bowl_converges():
+    h0, a, L, amp = 1.0, 200.0, 600.0, 20.0
+    T = 2 * np.pi / A.bowl_omega(h0, a)
+    errs = []
+    for nx, dx in [(300, 2.0), (600, 1.0)]:
+        sc = inputs.parabolic_bowl(nx=nx, ny=3, dx=dx, dtype=F64)
+        o = oracle.Oracle.from_scenario(sc)
+        s = run_to(o, 0.3 * T)
+        h, hu, _ = o.state()
+        x = (np.arange(nx) + 0.5) * dx
+        errs.append(A.rel_l2(h[1], A.bowl_h(x, s["t"], h0, a, L, amp)))
+        # velocity in the wet core follows amp * omega * sin(omega t)
+        core = A.bowl_h(x, s["t"], h0, a, L, amp) > 0.3
+        u = hu[1][core] / h[1][core]
+        assert abs(np.median(u) - A.bowl_u(s["t"], h0, a, amp)) < 0.05 * amp * A.bowl_omega(h0, a)
+    assert errs[0] < 0.05 and errs[1] < 0.02
+    assert errs[0] / errs[1] > 2.0
+
+
+def test_mass_balance_with_clamping():
+    # |M(t) - M(0) - clamp(t)| / M(0) <= 1e-12, with clamping active
+    sc = inputs.parabolic_bowl(nx=300, ny=3, dx=2.0, dtype=F64)
+    o = oracle.Oracle.from_scenario(sc)
+    m0 = o.scalars()["mass"]
+    o.step(300)
+    s = o.scalars()
+    assert s["clamp_mass"] > 1e-3 * m0
+    assert abs(s["mass"] - m0 - s["clamp_mass"]) <= 1e-12 * m0
+
+
+# ---------------------------------------------------------------------------
+# Steady flow down a slope with friction (Section 2.3)
+# ---------------------------------------------------------------------------
+
+def test_manning_discharge_value():
+    # n = 0.033, slope 1/20, depth 0.5 (Section 2.3)
+    assert abs(A.manning_q(0.5, 1 / 20, 0.033) - 2.1342947832) < 1e-9
+
+
+def test_steady_slope_is_discrete_steady_state():
+    sc = inputs.steady_slope(dtype=F64)
+    o = oracle.Oracle.from_scenario(sc)
+    Lh, Lhu, Lhv = o.rhs()
+    assert np.abs(Lh).max() < 1e-12
+    assert np.abs(Lhu).max() < 1e-12
+    assert np.abs(Lhv).max() == 0.0
+
+
+def test_steady_slope_relaxes_to_manning_flow():
+    sc = inputs.steady_slope(perturb=0.05, dtype=F64)
+    o = oracle.Oracle.from_scenario(sc)
+    q = A.manning_q(0.5, 1 / 20, 0.033)
+    run_to(o, 5.0)
+    h, hu, _ = o.state()
+    assert A.rel_linf(hu, np.full_like(hu, q)) > 1e-3  # still perturbed
+    run_to(o, 100.0)
+    h, hu, _ = o.state()
+    assert A.rel_linf(hu, np.full_like(hu, q)) < 1e-10
+    assert A.rel_linf(h, np.full_like(h, 0.5)) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Lake at rest (bed source after Xing & Shu, Methods)
+# ---------------------------------------------------------------------------
+
+def test_lake_at_rest_preserved_to_roundoff():
+    sc = inputs.lake_at_rest(dtype=F64)
+    o = oracle.Oracle.from_scenario(sc)
+    assert o.step(1000) == 0
+    h, hu, hv = o.state()
+    assert np.abs(hu).max() <= 1e-10 and np.abs(hv).max() <= 1e-10
+    assert np.abs(h + sc.b - 1.7).max() <= 1e-11
+
+
+def test_lake_at_rest_with_friction_and_anisotropic_cells():
+    sc = inputs.lake_at_rest(nx=40, ny=24, dx=1.0, dy=2.5, manning=0.05, dtype=F64)
+    o = oracle.Oracle.from_scenario(sc)
+    o.step(300)
+    h, hu, hv = o.state()
+    assert np.abs(hu).max() <= 1e-10 and np.abs(hv).max() <= 1e-10
+    assert np.abs(h + sc.b - 1.7).max() <= 1e-11
+
+
+# ---------------------------------------------------------------------------
+# TVD-RK3 (Methods, Eq. (8)): third order in time
+# ---------------------------------------------------------------------------
+
+def test_rk3_third_order_in_time():
+    nx = 80
+    x = (np.arange(nx) + 0.5)
+    h = 1.0 + 0.1 * np.exp(-((x - 40.0) / 6.0) ** 2)
+    z = np.zeros((3, nx))
+    H = np.broadcast_to(h, (3, nx)).copy()
+
+    def run(dt, T=4.0):
+        p = inputs.Params(nx, 3, 1.0, 1.0, cfl=0.0, dt_fixed=dt)
+        o = oracle.Oracle(p, z, z, H, z, z)
+        o.step(int(round(T / dt)))
+        return o.state()[0][1]
+
+    ref = run(0.00625)
+    e = [np.abs(run(dt) - ref).max() for dt in (0.2, 0.1, 0.05)]
+    r1, r2 = e[0] / e[1], e[1] / e[2]
+    assert 6.0 < r1 < 10.0 and 6.0 < r2 < 10.0
+
+
+# ---------------------------------------------------------------------------
+# Exact symmetries of the discrete operator
+# ---------------------------------------------------------------------------
+
+def _run(sc, n):
+    o = oracle.Oracle.from_scenario(sc)
+    assert o.step(n) == 0
+    return o.state(), o.scalars()
+
+
+def test_transpose_symmetry_bitwise():
+    sc = inputs.random_wet(37, 23, seed=4, dry_fraction=0.05)
+    (h, hu, hv), s = _run(sc, 12)
+    (hT, huT, hvT), sT = _run(inputs.transpose(sc), 12)
+    assert np.array_equal(hT, h.T) and np.array_equal(huT, hv.T) and np.array_equal(hvT, hu.T)
+    assert s["t"] == sT["t"]
+
+
+def test_mirror_symmetry_bitwise():
+    sc = inputs.random_wet(33, 17, seed=9, dry_fraction=0.05)
+    (h, hu, hv), _ = _run(sc, 12)
+    (hM, huM, hvM), _ = _run(inputs.mirror_x(sc), 12)
+    assert np.array_equal(hM, h[:, ::-1])
+    assert np.array_equal(huM, -hu[:, ::-1])
+    assert np.array_equal(hvM, hv[:, ::-1])
+
+
+def test_runup_is_non_decreasing():
+    sc = inputs.parabolic_bowl(nx=300, ny=3, dx=2.0)
+    o = oracle.Oracle.from_scenario(sc)
+    r = [o.scalars()["runup"]]
+    for _ in range(10):
+        o.step(40)
+        r.append(o.scalars()["runup"])
+    assert all(b >= a for a, b in zip(r, r[1:]))
+
+
+def test_invalid_inputs_rejected():
+    sc = inputs.dam_break(nx=8, ny=4)
+    bad = sc.h.copy()
+    bad[1, 1] = np.nan
+    with pytest.raises(ValueError):
+        oracle.Oracle(sc.params, sc.b, sc.n, bad, sc.hu, sc.hv)
+    bad = sc.h.copy()
+    bad[0, 0] = -1.0
+    with pytest.raises(ValueError):
+        oracle.Oracle(sc.params, sc.b, sc.n, bad, sc.hu, sc.hv)
+    small = inputs.dam_break(nx=2, ny=4)
+    with pytest.raises(ValueError):
+        oracle.Oracle.from_scenario(small)
