@@ -1,0 +1,228 @@
+/*
+ * swe.h - C ABI of the MI355X shallow-water step library (libswe.so).
+ *
+ * The library advances the 2-D nonlinear shallow-water equations of Madden,
+ * Marras & Suckale (arXiv 2301.12010), Methods, Eqs. (1)-(3), in the vector
+ * form u_t + F_x + G_y = S of Eq. (4) with u = (h, hu, hv):
+ *   - fifth-order WENO reconstruction at every half-step face (Methods, WENO
+ *     paragraph) of the Lax-Friedrichs split fluxes F+- = (F +- alpha u~)/2,
+ *     u~ = (h + b, hu, hv), with alpha the global maximum characteristic
+ *     speed of each RK stage (Methods, Lax-Friedrichs paragraph, Eq. (6));
+ *   - the bed source -g (h + b) grad b, centred at the cell, its face values
+ *     of b reconstructed with the normal-momentum flux's WENO weights, and the
+ *     explicit Manning friction -g n^2 |q| q / h^(7/3) (Eqs. (2)-(3), (7));
+ *   - the three-stage TVD Runge-Kutta update of Eq. (8).
+ * All arithmetic of the state is FP32 on the GPU; FP64 is kept for time and
+ * the mass diagnostics.  No call takes or returns a torch type.
+ *
+ * Arrays are row-major [ny][nx] float32 with x fastest (element (i, j) at
+ * j * nx + i).  Input and output pointers may be host or device memory; the
+ * runtime's unified addressing tells them apart.  Callers keep ownership of
+ * every array they pass; the library copies inputs and owns its device
+ * buffers.  No function throws; each returns an SWE_* code.
+ */
+#ifndef SWE_H
+#define SWE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define SWE_OK 0
+#define SWE_EINVAL (-1)     /* bad argument: sizes, spacing, non-finite or negative field */
+#define SWE_ENOMEM (-2)     /* device allocation failed or the memory budget is exceeded */
+#define SWE_EDEVICE (-3)    /* a HIP runtime call failed */
+#define SWE_ENONFINITE (-4) /* a wave speed became non-finite; the state is poisoned */
+#define SWE_EBUSY (-5)      /* the server's request queue is full */
+#define SWE_ENOTFOUND (-6)  /* unknown ticket or scenario index */
+
+/* ---- boundary kinds (per side: west, east, south, north) ---------------- */
+/* REFLECT: three mirrored ghost layers, normal momentum odd (the free-slip,
+ *          no-penetration walls of Section 2.4 and the reflective walls of the
+ *          dam-break workload).
+ * FIXED:   ghost (h, hu, hv) frozen at the create-time values of the nearest
+ *          interior cell, bed extended linearly: the constant-height zero-flux
+ *          (Section 2.1), Dirichlet (Section 2.2) and inflow/outflow
+ *          (Section 2.3) conditions of the verification problems. */
+#define SWE_BC_REFLECT 0
+#define SWE_BC_FIXED 1
+
+/* Problem parameters (plain data, copied by the library). */
+typedef struct swe_params {
+    int32_t nx, ny;    /* cells in x and y; each >= 3 */
+    double dx, dy;     /* cell sizes [m], > 0 */
+    double g;          /* gravity [m/s^2]; the paper uses 9.81 */
+    double cfl;        /* > 0: dt = cfl / (alpha_x/dx + alpha_y/dy) from u^n;
+                          <= 0: fixed dt = dt_fixed (the paper's runs use 5e-3) */
+    double dt_fixed;   /* used when cfl <= 0; must then be > 0 */
+    double h_dry;      /* wet/dry threshold [m]: wet <=> h > h_dry */
+    double weno_eps;   /* WENO5 epsilon added to the smoothness indicators */
+    double kappa_cap;  /* > 0: friction rate capped at kappa_cap/dt; <= 0: no cap */
+    int32_t bc[4];     /* SWE_BC_* for west, east, south, north */
+} swe_params;
+
+/* Diagnostics returned with a read. */
+typedef struct swe_stats {
+    double t;          /* simulated time [s] (FP64 sum of the step sizes) */
+    int64_t step;      /* completed RK3 steps */
+    double mass;       /* sum of h dx dy over the grid (FP64 sum of the FP32 state) */
+    double clamp_mass; /* mass added by clamping h < 0 to 0, weighted by how much
+                          of each stage's clamp reaches u^(n+1) (1/6, 2/3, 1) */
+    double dt;         /* step size of the next step (from the current state) */
+    float alpha_x;     /* global max |u| + sqrt(g h) of the current state */
+    float alpha_y;     /* global max |v| + sqrt(g h) */
+    float runup;       /* max bed elevation b > 0 of any wet cell so far (0 if none) */
+    int32_t status;    /* SWE_OK or SWE_ENONFINITE */
+} swe_stats;
+
+/* ---- single scenario ---------------------------------------------------- */
+typedef struct swe_ctx swe_ctx;
+
+/* Create a scenario on the current HIP device.  b is the bed elevation [m],
+ * manning_n the Manning coefficient per cell, (h0, hu0, hv0) the initial
+ * state; all [ny][nx] float32, host or device.  hip_stream is a hipStream_t
+ * (NULL: the library creates its own); every later call of this context is
+ * ordered on it.  Errors: SWE_EINVAL for nx or ny < 3, dx or dy <= 0,
+ * cfl <= 0 with dt_fixed <= 0, an unknown boundary kind, or any non-finite
+ * value, h0 < 0 or manning_n < 0; SWE_ENOMEM, SWE_EDEVICE otherwise.  On
+ * error *out is NULL. */
+int swe_create(const swe_params *p, const float *b, const float *manning_n,
+               const float *h0, const float *hu0, const float *hv0,
+               void *hip_stream, swe_ctx **out);
+
+/* Enqueue nsteps RK3 steps (three stage launches each, dt computed on the
+ * device).  Asynchronous; never blocks; a non-finite state surfaces at the
+ * next swe_read.  nsteps < 0 is SWE_EINVAL; 0 is a no-op. */
+int swe_step(swe_ctx *ctx, int32_t nsteps);
+
+/* Wait for the context's stream, then copy the state (any of h, hu, hv may
+ * be NULL) and the diagnostics (stats may be NULL).  Returns SWE_ENONFINITE
+ * once a wave speed became non-finite (the copies are still made). */
+int swe_read(swe_ctx *ctx, float *h, float *hu, float *hv, swe_stats *stats);
+
+/* Release the context's device memory.  NULL-safe. */
+void swe_destroy(swe_ctx *ctx);
+
+/* Context options (swe_set_option keys). */
+#define SWE_OPT_GRAPH_STEPS 1 /* steps per captured hipGraph segment; 0 = plain launches (default 32) */
+#define SWE_OPT_TILE 2        /* tile variant index, see swe_tile_info; -1 = automatic (default) */
+int swe_set_option(swe_ctx *ctx, int32_t key, int64_t value);
+
+/* Device addresses of the context's live state planes (h, hu, hv of u^n)
+ * and the row pitch in elements, for callers that keep results on the GPU.
+ * The planes change only through swe_step. */
+int swe_state_device(swe_ctx *ctx, float **h, float **hu, float **hv, int64_t *pitch);
+
+/* Measurement: run nsteps steps with plain launches, bracketing every stage
+ * kernel with HIP events on the context's stream; ms[0..2] receive the mean
+ * device duration of the stage-1, -2 and -3 launches.  Blocks until done. */
+int swe_time_stages(swe_ctx *ctx, int32_t nsteps, double *ms);
+
+/* ---- tile variants and autotuning --------------------------------------- */
+/* Tile variants of the stage kernel: tile width tx, height ty, cells per
+ * thread along a sweep r, threads per block. Results are bitwise identical
+ * across variants.  Returns SWE_ENOTFOUND past the last variant. */
+int swe_tile_info(int32_t index, int32_t *tx, int32_t *ty, int32_t *r, int32_t *threads);
+int swe_tile_count(void);
+
+/* Time every tile variant on a synthetic nx-by-ny problem and return the
+ * fastest.  With cache_path non-NULL the result is looked up in / added to
+ * that JSON file, keyed by (nx, ny, gfx arch). */
+int swe_autotune(int32_t nx, int32_t ny, const char *cache_path, int32_t *best_tile,
+                 double *best_ms_per_step);
+
+/* ---- batched scenarios (one persistent launch for all) ------------------ */
+typedef struct swe_batch swe_batch;
+
+/* Empty batch bound to hip_stream (NULL: own stream). */
+int swe_batch_create(void *hip_stream, swe_batch **out);
+
+/* Add a scenario with its own grid, fields and step count (>= 0); *index
+ * receives its position.  Same validation as swe_create. */
+int swe_batch_add(swe_batch *bt, const swe_params *p, const float *b, const float *manning_n,
+                  const float *h0, const float *hu0, const float *hv0, int32_t nsteps,
+                  int32_t *index);
+
+/* Advance every scenario by min(max_steps, its remaining steps) in one
+ * persistent launch (max_steps < 0: to completion).  Asynchronous. */
+int swe_batch_run(swe_batch *bt, int32_t max_steps);
+
+/* Wait, then copy scenario `index` (pointers may be NULL). */
+int swe_batch_read(swe_batch *bt, int32_t index, float *h, float *hu, float *hv, swe_stats *stats);
+
+/* Launch modes of swe_batch_run (swe_batch_set_mode). */
+#define SWE_BATCH_PERSISTENT 0 /* one persistent kernel, tile tickets, per-scenario barriers */
+#define SWE_BATCH_ROUNDS 1     /* one launch per stage covering every active scenario */
+int swe_batch_set_mode(swe_batch *bt, int32_t mode, int32_t use_graph);
+/* Tile variant used by the batch's launches (-1: automatic, from the
+ * scenario with most cells).  All variants give bitwise identical states. */
+int swe_batch_set_tile(swe_batch *bt, int32_t tile);
+void swe_batch_destroy(swe_batch *bt);
+
+/* ---- serving: continuous batching of scenario requests ------------------ */
+typedef struct swe_server swe_server;
+
+#define SWE_PENDING 0
+#define SWE_DONE 1
+#define SWE_FAILED 2
+#define SWE_CANCELLED 3
+
+typedef struct swe_result {
+    int32_t status;   /* SWE_PENDING, SWE_DONE, SWE_FAILED or SWE_CANCELLED */
+    int32_t error;    /* SWE_OK or the error that failed the request */
+    double t;         /* simulated time at completion */
+    double mass;
+    float runup;
+    int64_t steps;
+    double t_submit;  /* host monotonic seconds: submit, admission, result ready */
+    double t_admit;
+    double t_done;
+} swe_result;
+
+typedef struct swe_server_stats {
+    int64_t submitted, completed, failed, cancelled, queued, active;
+    size_t mem_in_use, mem_high_water, mem_budget;
+    int64_t segments;  /* persistent launches so far */
+} swe_server_stats;
+
+/* Start a server on `device` with a device-memory budget for scenario state
+ * (bytes; 0 = 80% of free memory), at most max_slots resident scenarios, and
+ * segment_steps steps per persistent launch between admissions. */
+int swe_server_create(int32_t device, size_t mem_budget, int32_t max_slots,
+                      int32_t segment_steps, swe_server **out);
+
+/* Queue a request; inputs are copied before return.  Returns SWE_EINVAL for
+ * bad input, SWE_ENOMEM if it can never fit the budget, SWE_EBUSY if the
+ * queue is full. */
+int swe_submit(swe_server *sv, const swe_params *p, const float *b, const float *manning_n,
+               const float *h0, const float *hu0, const float *hv0, int32_t nsteps,
+               uint64_t *ticket);
+
+/* Non-blocking.  Fills r; when r->status is DONE the state is copied into
+ * the non-NULL h, hu, hv (host memory).  A ticket is released after a final
+ * status (DONE, FAILED, CANCELLED) has been returned once; afterwards it is
+ * SWE_ENOTFOUND. */
+int swe_poll(swe_server *sv, uint64_t ticket, swe_result *r, float *h, float *hu, float *hv);
+
+/* Cancel a queued or running request (it ends as SWE_CANCELLED). */
+int swe_cancel(swe_server *sv, uint64_t ticket);
+
+int swe_server_get_stats(swe_server *sv, swe_server_stats *st);
+
+/* Stop the server thread and free its memory.  NULL-safe. */
+void swe_server_destroy(swe_server *sv);
+
+/* ---- misc ----------------------------------------------------------------- */
+const char *swe_strerror(int code);
+
+/* Bytes of device memory one nx-by-ny scenario occupies. */
+size_t swe_footprint(int32_t nx, int32_t ny);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SWE_H */

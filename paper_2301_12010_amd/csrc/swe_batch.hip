@@ -1,0 +1,398 @@
+// swe_batch.hip - many scenarios of uneven sizes and step counts advanced
+// together.
+//
+// Schedule.  A run advances scenario s by k_s = min(max_steps, remaining_s)
+// steps.  Scenarios are ordered by k_s (descending), so the scenarios taking
+// part in round r (round = one stage of one step: r = 3*step + stage - 1)
+// are a prefix of that order, of length A(r).  The tiles of round r are the
+// tiles of those scenarios, numbered scenario after scenario.
+//
+// PERSISTENT mode: one kernel for the whole run.  Tiles are numbered round
+// after round ("tickets"); each block repeatedly takes the next group of
+// tickets with one atomic, maps a ticket to (round, scenario, tile) by binary
+// search in two small tables, waits until every tile of the scenario's
+// previous round has completed (per-scenario counter, acquire at agent
+// scope), runs the stage on the tile, and bumps the counter (release).  A
+// ticket only ever waits on smaller tickets, and tickets are taken by running
+// blocks, so the smallest unfinished ticket can always proceed: the kernel
+// cannot deadlock and needs no co-residency guarantee.
+//
+// ROUNDS mode: one launch per round over the tiles of all its scenarios;
+// kernel boundaries order the rounds.  Optionally captured as one hipGraph.
+//
+// Both modes run the same stage code per tile, so every scenario's state is
+// bitwise identical to a run of that scenario alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "swe_internal.hpp"
+
+namespace swe {
+
+__device__ __forceinline__ int xcd_remap_b(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, l = b >> 3;
+    return x * q + (x < r ? x : r) + l;
+}
+
+// Largest i in [0, n) with a[i] <= v (a ascending, a[0] <= v).
+template <class T>
+__device__ __forceinline__ int upper_index(const T *a, int n, T v)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+struct BatchTables {
+    const Geo *geo;            // per scenario (batch order)
+    const int *order;          // sorted position -> scenario
+    const int *prefix;         // tile prefix over sorted positions (size nact + 1)
+    const int *ntx;            // tiles along x per sorted position
+    const long long *rstart;   // first ticket of each round (size nrounds + 1)
+    const int *ractive;        // active prefix length per round
+    unsigned int *done;        // completed tiles per sorted position (this run)
+    unsigned long long *ticket;
+    int nrounds, nact, group;
+};
+
+template <class C>
+__global__ __launch_bounds__(C::NT, 2) void k_persistent(BatchTables T)
+{
+    __shared__ float lds[C::LDS_FLOATS];
+    __shared__ long long s_ticket;
+    const long long total = T.rstart[T.nrounds];
+    for (;;) {
+        if (threadIdx.x == 0) s_ticket = (long long)atomicAdd(T.ticket, (unsigned long long)T.group);
+        __syncthreads();
+        const long long t0 = s_ticket;
+        __syncthreads();
+        if (t0 >= total) break;
+        const long long t1 = t0 + T.group < total ? t0 + T.group : total;
+        for (long long t = t0; t < t1; ++t) {
+            const int r = upper_index(T.rstart, T.nrounds, t);
+            const int l = (int)(t - T.rstart[r]);
+            const int slot = upper_index(T.prefix, T.ractive[r], l);
+            const int tl = l - T.prefix[slot];
+            const int ntx = T.ntx[slot];
+            const int ntiles = T.prefix[slot + 1] - T.prefix[slot];
+            const Geo &G = T.geo[T.order[slot]];
+            // every tile of this scenario's previous round must be complete
+            if (threadIdx.x == 0) {
+                const unsigned int need = (unsigned int)ntiles * (unsigned int)r;
+                while (__hip_atomic_load(&T.done[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need)
+                    __builtin_amdgcn_s_sleep(1);
+            }
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            stage_tile<C>(G, tl % ntx, tl / ntx, lds, r % 3 + 1);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                __hip_atomic_fetch_add(&T.done[slot], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
+template <class C, int S>
+__global__ __launch_bounds__(C::NT, 2) void k_round(BatchTables T, int nact_round, int nblocks)
+{
+    __shared__ float lds[C::LDS_FLOATS];
+    const int id = xcd_remap_b(blockIdx.x, nblocks);
+    const int slot = upper_index(T.prefix, nact_round, id);
+    const int tl = id - T.prefix[slot];
+    const int ntx = T.ntx[slot];
+    stage_tile<C>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, S);
+}
+
+// Clears the run's counters (a kernel, so graph replays need no memset node).
+__global__ void k_zero_counters(unsigned int *done, int n, unsigned long long *ticket)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) done[i] = 0u;
+    if (threadIdx.x == 0) *ticket = 0ull;
+}
+
+struct BatchKernels {
+    void (*persistent)(BatchTables);
+    void (*round[3])(BatchTables, int, int);
+};
+
+#define SWE_BK(TX, TY, R)                                                                          \
+    {k_persistent<TileCfg<TX, TY, R>>,                                                             \
+     {k_round<TileCfg<TX, TY, R>, 1>, k_round<TileCfg<TX, TY, R>, 2>, k_round<TileCfg<TX, TY, R>, 3>}},
+
+// same order as the single-scenario variant table
+static const BatchKernels g_bk[] = {SWE_BK(64, 16, 8) SWE_BK(64, 32, 8) SWE_BK(32, 32, 8)
+                                        SWE_BK(64, 16, 4) SWE_BK(128, 16, 8)};
+
+// ---------------------------------------------------------------------------
+// segment launcher (shared by swe_batch and the server)
+// ---------------------------------------------------------------------------
+static size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+SegmentLauncher::~SegmentLauncher()
+{
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (dmem) (void)hipFree(dmem);
+}
+
+int SegmentLauncher::run(const std::vector<Geo> &geos, const std::vector<int> &ksteps, int vi, int mode,
+                         bool use_graph, hipStream_t stream)
+{
+    const Variant &v = variant(vi);
+    const BatchKernels &K = g_bk[vi];
+    const int n = (int)geos.size();
+    std::vector<int> act;
+    for (int i = 0; i < n; ++i)
+        if (ksteps[i] > 0) act.push_back(i);
+    if (act.empty()) return SWE_OK;
+    std::stable_sort(act.begin(), act.end(), [&](int a, int b) { return ksteps[a] > ksteps[b]; });
+    const int nact = (int)act.size();
+    const int nrounds = 3 * ksteps[act[0]];
+
+    std::vector<int> prefix(nact + 1, 0), ntx(nact), order(nact);
+    for (int q = 0; q < nact; ++q) {
+        const Geo &g = geos[act[q]];
+        const int tx = (g.nx + v.tx - 1) / v.tx, ty = (g.ny + v.ty - 1) / v.ty;
+        ntx[q] = tx;
+        order[q] = act[q];
+        prefix[q + 1] = prefix[q] + tx * ty;
+    }
+    std::vector<int> ractive(nrounds);
+    std::vector<long long> rstart(nrounds + 1, 0);
+    {
+        int a = nact;
+        for (int r = 0; r < nrounds; ++r) {
+            while (a > 0 && 3 * ksteps[act[a - 1]] <= r) --a;
+            ractive[r] = a;
+            rstart[r + 1] = rstart[r] + prefix[a];
+        }
+    }
+
+    const size_t o_geo = 0, o_order = o_geo + al(n * sizeof(Geo));
+    const size_t o_prefix = o_order + al(nact * sizeof(int));
+    const size_t o_ntx = o_prefix + al((nact + 1) * sizeof(int));
+    const size_t o_rstart = o_ntx + al(nact * sizeof(int));
+    const size_t o_ract = o_rstart + al((nrounds + 1) * sizeof(long long));
+    const size_t o_done = o_ract + al(nrounds * sizeof(int));
+    const size_t o_ticket = o_done + al(nact * sizeof(unsigned int));
+    const size_t need = o_ticket + al(sizeof(unsigned long long));
+    SWE_HIP_TRY(hipStreamSynchronize(stream));  // the previous segment's tables are free
+    if (graph) {
+        (void)hipGraphExecDestroy(graph);
+        graph = nullptr;
+    }
+    if (need > dbytes) {
+        if (dmem) (void)hipFree(dmem);
+        dmem = nullptr;
+        dbytes = 0;
+        if (hipMalloc(&dmem, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return SWE_ENOMEM;
+        }
+        dbytes = need;
+    }
+    if (cus <= 0) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (cus <= 0) cus = 256;
+    }
+    hbuf.assign(o_done, 0);
+    char *hb = hbuf.data();
+    std::memcpy(hb + o_geo, geos.data(), n * sizeof(Geo));
+    std::memcpy(hb + o_order, order.data(), nact * sizeof(int));
+    std::memcpy(hb + o_prefix, prefix.data(), (nact + 1) * sizeof(int));
+    std::memcpy(hb + o_ntx, ntx.data(), nact * sizeof(int));
+    std::memcpy(hb + o_rstart, rstart.data(), (nrounds + 1) * sizeof(long long));
+    std::memcpy(hb + o_ract, ractive.data(), nrounds * sizeof(int));
+    SWE_HIP_TRY(hipMemcpyAsync(dmem, hb, o_done, hipMemcpyHostToDevice, stream));
+
+    char *dm = static_cast<char *>(dmem);
+    BatchTables T;
+    T.geo = reinterpret_cast<const Geo *>(dm + o_geo);
+    T.order = reinterpret_cast<const int *>(dm + o_order);
+    T.prefix = reinterpret_cast<const int *>(dm + o_prefix);
+    T.ntx = reinterpret_cast<const int *>(dm + o_ntx);
+    T.rstart = reinterpret_cast<const long long *>(dm + o_rstart);
+    T.ractive = reinterpret_cast<const int *>(dm + o_ract);
+    T.done = reinterpret_cast<unsigned int *>(dm + o_done);
+    T.ticket = reinterpret_cast<unsigned long long *>(dm + o_ticket);
+    T.nrounds = nrounds;
+    T.nact = nact;
+    T.group = group;
+
+    auto enqueue = [&]() -> int {
+        if (mode == SWE_BATCH_PERSISTENT) {
+            hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(256), 0, stream, T.done, nact, T.ticket);
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, K.persistent, v.nt, 0) != hipSuccess ||
+                per_cu <= 0)
+                per_cu = 1;
+            long long grid = (long long)per_cu * cus;
+            if (grid > rstart[nrounds]) grid = rstart[nrounds];
+            hipLaunchKernelGGL(K.persistent, dim3((unsigned)grid), dim3(v.nt), 0, stream, T);
+        } else {
+            for (int r = 0; r < nrounds; ++r) {
+                const int nb = prefix[ractive[r]];
+                hipLaunchKernelGGL(K.round[r % 3], dim3(nb), dim3(v.nt), 0, stream, T, ractive[r], nb);
+            }
+        }
+        return hipGetLastError() == hipSuccess ? SWE_OK : SWE_EDEVICE;
+    };
+
+    if (use_graph) {
+        hipGraph_t g = nullptr;
+        SWE_HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue();
+        const hipError_t e = hipStreamEndCapture(stream, &g);
+        if (rc || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc ? rc : SWE_EDEVICE;
+        }
+        const hipError_t ie = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            graph = nullptr;
+            return SWE_EDEVICE;
+        }
+        SWE_HIP_TRY(hipGraphLaunch(graph, stream));
+        return SWE_OK;
+    }
+    return enqueue();
+}
+
+}  // namespace swe
+
+using namespace swe;
+
+struct BatchScen {
+    swe_params p{};
+    DevScenario d;
+    int total = 0;  // requested steps
+    int done = 0;   // steps enqueued so far
+};
+
+struct swe_batch {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<BatchScen> sc;
+    int mode = SWE_BATCH_PERSISTENT;
+    bool use_graph = false;
+    int tile = -1;
+    SegmentLauncher seg;
+};
+
+static int batch_variant(const swe_batch *bt)
+{
+    if (bt->tile >= 0) return bt->tile;
+    // the variant preferred for the scenario carrying most cells
+    size_t best = 0;
+    int nx = 0, ny = 0;
+    for (const auto &s : bt->sc)
+        if ((size_t)s.p.nx * s.p.ny > best) {
+            best = (size_t)s.p.nx * s.p.ny;
+            nx = s.p.nx;
+            ny = s.p.ny;
+        }
+    return default_variant(nx, ny);
+}
+
+extern "C" {
+
+int swe_batch_create(void *hip_stream, swe_batch **out)
+{
+    if (!out) return SWE_EINVAL;
+    *out = nullptr;
+    swe_batch *bt = new (std::nothrow) swe_batch();
+    if (!bt) return SWE_ENOMEM;
+    if (hip_stream) {
+        bt->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&bt->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete bt;
+            return SWE_EDEVICE;
+        }
+        bt->own_stream = true;
+    }
+    *out = bt;
+    return SWE_OK;
+}
+
+int swe_batch_add(swe_batch *bt, const swe_params *p, const float *b, const float *n, const float *h0,
+                  const float *hu0, const float *hv0, int32_t nsteps, int32_t *index)
+{
+    if (!bt || nsteps < 0) return SWE_EINVAL;
+    HostFields f;
+    int rc = load_fields(p, b, n, h0, hu0, hv0, f);
+    if (rc) return rc;
+    BatchScen s;
+    s.p = *p;
+    s.total = nsteps;
+    SWE_HIP_TRY(hipStreamSynchronize(bt->stream));
+    rc = scenario_upload(*p, f, bt->stream, s.d);
+    if (rc) return rc;
+    bt->sc.push_back(s);
+    if (index) *index = (int32_t)bt->sc.size() - 1;
+    return SWE_OK;
+}
+
+int swe_batch_set_mode(swe_batch *bt, int32_t mode, int32_t use_graph)
+{
+    if (!bt || (mode != SWE_BATCH_PERSISTENT && mode != SWE_BATCH_ROUNDS)) return SWE_EINVAL;
+    bt->mode = mode;
+    bt->use_graph = use_graph != 0;
+    return SWE_OK;
+}
+
+int swe_batch_set_tile(swe_batch *bt, int32_t tile)
+{
+    if (!bt || tile < -1 || tile >= variant_count()) return SWE_EINVAL;
+    bt->tile = tile;
+    return SWE_OK;
+}
+
+int swe_batch_run(swe_batch *bt, int32_t max_steps)
+{
+    if (!bt) return SWE_EINVAL;
+    std::vector<Geo> geos;
+    std::vector<int> ks;
+    for (auto &s : bt->sc) {
+        int k = s.total - s.done;
+        if (max_steps >= 0 && k > max_steps) k = max_steps;
+        geos.push_back(s.d.geo);
+        ks.push_back(k);
+    }
+    const int rc = bt->seg.run(geos, ks, batch_variant(bt), bt->mode, bt->use_graph, bt->stream);
+    if (rc) return rc;
+    for (size_t i = 0; i < bt->sc.size(); ++i) bt->sc[i].done += ks[i];
+    return SWE_OK;
+}
+
+int swe_batch_read(swe_batch *bt, int32_t index, float *h, float *hu, float *hv, swe_stats *st)
+{
+    if (!bt) return SWE_EINVAL;
+    if (index < 0 || index >= (int)bt->sc.size()) return SWE_ENOTFOUND;
+    return scenario_read(bt->sc[index].d, bt->stream, h, hu, hv, st);
+}
+
+void swe_batch_destroy(swe_batch *bt)
+{
+    if (!bt) return;
+    if (bt->stream) (void)hipStreamSynchronize(bt->stream);
+    for (auto &s : bt->sc) scenario_free(s.d);
+    if (bt->own_stream && bt->stream) (void)hipStreamDestroy(bt->stream);
+    delete bt;  // the segment launcher frees its tables
+}
+
+}  // extern "C"

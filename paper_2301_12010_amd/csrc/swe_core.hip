@@ -1,0 +1,599 @@
+// swe_core.hip - single-scenario context, stage kernels and shared host code.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "swe_internal.hpp"
+
+namespace swe {
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+// Blocks are dispatched round-robin over the 8 XCDs; renumber them so that
+// each XCD receives a contiguous band of tiles and shares halo rows in its L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, l = b >> 3;
+    return x * q + (x < r ? x : r) + l;
+}
+
+template <class C, int S>
+__global__ __launch_bounds__(C::NT, 2) void k_stage(Geo G, int ntx, int nblocks)
+{
+    __shared__ float lds[C::LDS_FLOATS];
+    const int id = xcd_remap(blockIdx.x, nblocks);
+    stage_tile<C>(G, id % ntx, id / ntx, lds, S);
+}
+
+// Wave speeds (slot 0) and runup of the initial state.
+__global__ __launch_bounds__(256) void k_init(Geo G)
+{
+    __shared__ unsigned int ru[3 * 4];
+    __shared__ double rd[4];
+    unsigned int sx = 0, sy = 0, rb = 0;
+    double hs = 0.0;
+    const long long n = (long long)G.nx * G.ny;
+    for (long long e = blockIdx.x * 256ll + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+        const int j = (int)(e / G.nx), i = (int)(e - (long long)j * G.nx);
+        const int gi = j * G.pitch + i;
+        const float h = G.U[0][gi], hu = G.U[1][gi], hv = G.U[2][gi];
+        const bool wet = h > G.h_dry;
+        const float cel = sqrtf(G.g * fmaxf(h, 0.f));
+        const float inv = wet ? 1.f / h : 0.f;
+        const bool fin = fabsf(h) <= 3.4e38f && fabsf(hu) <= 3.4e38f && fabsf(hv) <= 3.4e38f;
+        const unsigned int bx = fin ? speed_bits(fabsf(hu * inv) + cel) : 0x7f800000u;
+        const unsigned int by = fin ? speed_bits(fabsf(hv * inv) + cel) : 0x7f800000u;
+        sx = bx > sx ? bx : sx;
+        sy = by > sy ? by : sy;
+        hs += (double)h;
+        const float b = G.b[gi];
+        if (wet && b > 0.f) rb = __float_as_uint(b) > rb ? __float_as_uint(b) : rb;
+    }
+    sx = wave_max_u32(sx);
+    sy = wave_max_u32(sy);
+    rb = wave_max_u32(rb);
+    hs = wave_sum_f64(hs);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        ru[wv] = sx;
+        ru[4 + wv] = sy;
+        ru[8 + wv] = rb;
+        rd[wv] = hs;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int mx = 0, my = 0, mr = 0;
+        double s = 0.0;
+        for (int w = 0; w < 4; ++w) {
+            mx = ru[w] > mx ? ru[w] : mx;
+            my = ru[4 + w] > my ? ru[4 + w] : my;
+            mr = ru[8 + w] > mr ? ru[8 + w] : mr;
+            s += rd[w];
+        }
+        atomicMax(&G.sd->alpha[0][0], mx);
+        atomicMax(&G.sd->alpha[0][1], my);
+        if (mr) atomicMax(&G.sd->runup, mr);
+        (void)s;
+        if (mx >= 0x7f800000u || my >= 0x7f800000u) atomicOr(&G.sd->flags, 1u);
+    }
+}
+
+// FP64 mass: MASS_BLOCKS blocks write fixed-order partial sums of h, then one
+// block adds them in order, so the result does not depend on scheduling.
+__global__ __launch_bounds__(256) void k_mass_part(Geo G)
+{
+    __shared__ double rd[4];
+    double hs = 0.0;
+    const long long n = (long long)G.nx * G.ny;
+    for (long long e = blockIdx.x * 256ll + threadIdx.x; e < n; e += (long long)MASS_BLOCKS * 256) {
+        const int j = (int)(e / G.nx), i = (int)(e - (long long)j * G.nx);
+        hs += (double)G.U[0][j * G.pitch + i];
+    }
+    hs = wave_sum_f64(hs);
+    if ((threadIdx.x & 63) == 0) rd[threadIdx.x >> 6] = hs;
+    __syncthreads();
+    if (threadIdx.x == 0) G.mass_part[blockIdx.x] = ((rd[0] + rd[1]) + rd[2]) + rd[3];
+}
+
+__global__ __launch_bounds__(64) void k_mass_final(Geo G)
+{
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int b = 0; b < MASS_BLOCKS; ++b) s += G.mass_part[b];
+        G.sd->mass_sum = s;
+    }
+}
+
+int launch_mass(const Geo &g, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_mass_part, dim3(MASS_BLOCKS), dim3(256), 0, stream, g);
+    hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(64), 0, stream, g);
+    return hipGetLastError() == hipSuccess ? SWE_OK : SWE_EDEVICE;
+}
+
+// ---------------------------------------------------------------------------
+// tile variants
+// ---------------------------------------------------------------------------
+#define SWE_TILE_LIST(X) \
+    X(64, 16, 8)         \
+    X(64, 32, 8)         \
+    X(32, 32, 8)         \
+    X(64, 16, 4)         \
+    X(128, 16, 8)
+
+#define SWE_VARIANT(TX, TY, R)                                                          \
+    {TX, TY, R, TileCfg<TX, TY, R>::NT, sizeof(float) * TileCfg<TX, TY, R>::LDS_FLOATS, \
+     {k_stage<TileCfg<TX, TY, R>, 1>, k_stage<TileCfg<TX, TY, R>, 2>, k_stage<TileCfg<TX, TY, R>, 3>}},
+
+static const Variant g_variants[] = {SWE_TILE_LIST(SWE_VARIANT)};
+
+int variant_count() { return (int)(sizeof(g_variants) / sizeof(g_variants[0])); }
+const Variant &variant(int i) { return g_variants[i]; }
+
+int launch_stage(const Variant &v, int stage, const Geo &g, hipStream_t stream)
+{
+    const int ntx = (g.nx + v.tx - 1) / v.tx, nty = (g.ny + v.ty - 1) / v.ty;
+    const int nb = ntx * nty;
+    hipLaunchKernelGGL(v.stage[stage - 1], dim3(nb), dim3(v.nt), 0, stream, g, ntx, nb);
+    return hipGetLastError() == hipSuccess ? SWE_OK : SWE_EDEVICE;
+}
+
+int launch_init(const Geo &g, hipStream_t stream)
+{
+    const long long n = (long long)g.nx * g.ny;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_init, dim3((unsigned)blocks), dim3(256), 0, stream, g);
+    return hipGetLastError() == hipSuccess ? SWE_OK : SWE_EDEVICE;
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+double now_seconds()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int validate_params(const swe_params *p)
+{
+    if (!p) return SWE_EINVAL;
+    if (p->nx < 3 || p->ny < 3) return SWE_EINVAL;
+    if ((long long)p->nx * p->ny > (1ll << 31) / 4) return SWE_EINVAL;
+    if (!(p->dx > 0.0) || !(p->dy > 0.0) || !std::isfinite(p->dx) || !std::isfinite(p->dy))
+        return SWE_EINVAL;
+    if (!(p->g > 0.0) || !std::isfinite(p->g)) return SWE_EINVAL;
+    if (!std::isfinite(p->cfl)) return SWE_EINVAL;
+    if (p->cfl <= 0.0 && !(p->dt_fixed > 0.0 && std::isfinite(p->dt_fixed))) return SWE_EINVAL;
+    if (!(p->h_dry >= 0.0) || !std::isfinite(p->h_dry)) return SWE_EINVAL;
+    if (!(p->weno_eps > 0.0) || !std::isfinite(p->weno_eps)) return SWE_EINVAL;
+    if (!std::isfinite(p->kappa_cap)) return SWE_EINVAL;
+    for (int s = 0; s < 4; ++s)
+        if (p->bc[s] != SWE_BC_REFLECT && p->bc[s] != SWE_BC_FIXED) return SWE_EINVAL;
+    return SWE_OK;
+}
+
+static int fetch(const float *src, size_t n, std::vector<float> &dst)
+{
+    if (!src) return SWE_EINVAL;
+    dst.resize(n);
+    hipPointerAttribute_t attr;
+    bool dev = false;
+    if (hipPointerGetAttributes(&attr, src) == hipSuccess)
+        dev = attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+    (void)hipGetLastError();
+    if (dev) {
+        SWE_HIP_TRY(hipMemcpy(dst.data(), src, n * sizeof(float), hipMemcpyDefault));
+    } else {
+        std::memcpy(dst.data(), src, n * sizeof(float));
+    }
+    return SWE_OK;
+}
+
+int load_fields(const swe_params *p, const float *b, const float *n, const float *h,
+                const float *hu, const float *hv, HostFields &f)
+{
+    int rc = validate_params(p);
+    if (rc) return rc;
+    const size_t N = (size_t)p->nx * p->ny;
+    f.nx = p->nx;
+    f.ny = p->ny;
+    if ((rc = fetch(b, N, f.b)) || (rc = fetch(n, N, f.n)) || (rc = fetch(h, N, f.h)) ||
+        (rc = fetch(hu, N, f.hu)) || (rc = fetch(hv, N, f.hv)))
+        return rc;
+    for (size_t k = 0; k < N; ++k) {
+        if (!std::isfinite(f.b[k]) || !std::isfinite(f.n[k]) || !std::isfinite(f.h[k]) ||
+            !std::isfinite(f.hu[k]) || !std::isfinite(f.hv[k]))
+            return SWE_EINVAL;
+        if (f.h[k] < 0.f || f.n[k] < 0.f) return SWE_EINVAL;
+    }
+    return SWE_OK;
+}
+
+std::vector<float> build_ghosts(const swe_params &p, const HostFields &f)
+{
+    const int nx = p.nx, ny = p.ny;
+    std::vector<float> g((size_t)24 * ny + (size_t)24 * nx, 0.f);
+    auto at = [&](const std::vector<float> &a, int i, int j) { return a[(size_t)j * nx + i]; };
+    for (int side = 0; side < 4; ++side) {
+        const int len = side < 2 ? ny : nx;
+        const size_t base = side == 0 ? 0 : side == 1 ? (size_t)12 * ny : side == 2 ? (size_t)24 * ny
+                                                                                     : (size_t)24 * ny + (size_t)12 * nx;
+        for (int k = 0; k < HALO; ++k)
+            for (int q = 0; q < len; ++q) {
+                int i0, j0, i1, j1;  // nearest and second-nearest interior cell
+                if (side == 0) { i0 = 0; j0 = q; i1 = 1; j1 = q; }
+                else if (side == 1) { i0 = nx - 1; j0 = q; i1 = nx - 2; j1 = q; }
+                else if (side == 2) { i0 = q; j0 = 0; i1 = q; j1 = 1; }
+                else { i0 = q; j0 = ny - 1; i1 = q; j1 = ny - 2; }
+                const double b0 = at(f.b, i0, j0), b1 = at(f.b, i1, j1);
+                const float vals[4] = {at(f.h, i0, j0), at(f.hu, i0, j0), at(f.hv, i0, j0),
+                                       (float)(b0 + (k + 1) * (b0 - b1))};
+                for (int fld = 0; fld < 4; ++fld) g[base + (size_t)(fld * 3 + k) * len + q] = vals[fld];
+            }
+    }
+    return g;
+}
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+size_t scenario_bytes(int nx, int ny)
+{
+    const size_t plane = align256((size_t)plane_pitch(nx) * ny * sizeof(float));
+    const size_t ghost = align256(((size_t)24 * ny + (size_t)24 * nx) * sizeof(float));
+    return 11 * plane + ghost + align256(sizeof(DevScen)) + align256(MASS_BLOCKS * sizeof(double));
+}
+
+int scenario_upload_into(void *mem, const swe_params &p, const HostFields &f, hipStream_t stream,
+                         DevScenario &d)
+{
+    const int nx = p.nx, ny = p.ny, pitch = plane_pitch(nx);
+    const size_t plane = align256((size_t)pitch * ny * sizeof(float));
+    char *base = static_cast<char *>(mem);
+    d.base = mem;
+    d.bytes = scenario_bytes(nx, ny);
+    Geo &g = d.geo;
+    g.nx = nx;
+    g.ny = ny;
+    g.pitch = pitch;
+    for (int s = 0; s < 4; ++s) g.bc[s] = p.bc[s];
+    g.dx = (float)p.dx;
+    g.dy = (float)p.dy;
+    g.inv_dx = (float)(1.0 / p.dx);
+    g.inv_dy = (float)(1.0 / p.dy);
+    g.g = (float)p.g;
+    g.half_g = (float)(0.5 * p.g);
+    g.h_dry = (float)p.h_dry;
+    g.eps12 = (float)(12.0 * p.weno_eps);
+    g.kappa_cap = (float)p.kappa_cap;
+    g.cfl = (float)p.cfl;
+    g.dt_fixed = (float)p.dt_fixed;
+    float *planes[11];
+    for (int k = 0; k < 11; ++k) planes[k] = reinterpret_cast<float *>(base + k * plane);
+    g.b = planes[0];
+    g.gn2 = planes[1];
+    for (int c = 0; c < 3; ++c) {
+        g.U[c] = planes[2 + c];
+        g.A[c] = planes[5 + c];
+        g.B[c] = planes[8 + c];
+    }
+    float *ghost = reinterpret_cast<float *>(base + 11 * plane);
+    g.ghost = ghost;
+    const size_t ghost_b = align256(((size_t)24 * ny + (size_t)24 * nx) * sizeof(float));
+    g.sd = reinterpret_cast<DevScen *>(base + 11 * plane + ghost_b);
+    g.mass_part = reinterpret_cast<double *>(base + 11 * plane + ghost_b + align256(sizeof(DevScen)));
+
+    const size_t N = (size_t)nx * ny;
+    std::vector<float> gn2(N);
+    for (size_t k = 0; k < N; ++k) gn2[k] = (float)(p.g * (double)f.n[k] * (double)f.n[k]);
+    std::vector<float> gh = build_ghosts(p, f);
+    const size_t row = (size_t)nx * sizeof(float), dpitch = (size_t)pitch * sizeof(float);
+    SWE_HIP_TRY(hipMemsetAsync(base, 0, 11 * plane, stream));
+    SWE_HIP_TRY(hipMemcpy2DAsync(planes[0], dpitch, f.b.data(), row, row, ny, hipMemcpyHostToDevice, stream));
+    SWE_HIP_TRY(hipMemcpy2DAsync(planes[1], dpitch, gn2.data(), row, row, ny, hipMemcpyHostToDevice, stream));
+    SWE_HIP_TRY(hipMemcpy2DAsync(planes[2], dpitch, f.h.data(), row, row, ny, hipMemcpyHostToDevice, stream));
+    SWE_HIP_TRY(hipMemcpy2DAsync(planes[3], dpitch, f.hu.data(), row, row, ny, hipMemcpyHostToDevice, stream));
+    SWE_HIP_TRY(hipMemcpy2DAsync(planes[4], dpitch, f.hv.data(), row, row, ny, hipMemcpyHostToDevice, stream));
+    SWE_HIP_TRY(hipMemcpyAsync(ghost, gh.data(), gh.size() * sizeof(float), hipMemcpyHostToDevice, stream));
+    SWE_HIP_TRY(hipMemsetAsync(g.sd, 0, sizeof(DevScen), stream));
+    int rc = launch_init(g, stream);
+    if (rc) return rc;
+    // the host vectors are freed on return: wait for the copies
+    SWE_HIP_TRY(hipStreamSynchronize(stream));
+    return SWE_OK;
+}
+
+int scenario_upload(const swe_params &p, const HostFields &f, hipStream_t stream, DevScenario &d)
+{
+    void *mem = nullptr;
+    const size_t bytes = scenario_bytes(p.nx, p.ny);
+    if (hipMalloc(&mem, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return SWE_ENOMEM;
+    }
+    const int rc = scenario_upload_into(mem, p, f, stream, d);
+    if (rc) {
+        (void)hipFree(mem);
+        d.base = nullptr;
+    }
+    return rc;
+}
+
+void scenario_free(DevScenario &d)
+{
+    if (d.base) (void)hipFree(d.base);
+    d.base = nullptr;
+}
+
+int stats_from_dev(const Geo &g, const DevScen &ds, swe_stats *st)
+{
+    const bool bad = (ds.flags & 1u) || ds.alpha[0][0] >= 0x7f800000u || ds.alpha[0][1] >= 0x7f800000u;
+    if (st) {
+        float ax, ay, ru;
+        std::memcpy(&ax, &ds.alpha[0][0], 4);
+        std::memcpy(&ay, &ds.alpha[0][1], 4);
+        std::memcpy(&ru, &ds.runup, 4);
+        st->t = ds.t;
+        st->step = ds.step;
+        st->mass = ds.mass_sum * (double)g.dx * (double)g.dy;
+        st->clamp_mass = ds.clamp_sum * (double)g.dx * (double)g.dy;
+        double dt = g.dt_fixed;
+        if (g.cfl > 0.f) {
+            const double den = (double)ax * (double)g.inv_dx + (double)ay * (double)g.inv_dy;
+            dt = (den > 0.0 && den < 1e300) ? (double)(float)((double)g.cfl / den) : 0.0;
+        }
+        st->dt = dt;
+        st->alpha_x = ax;
+        st->alpha_y = ay;
+        st->runup = ru;
+        st->status = bad ? SWE_ENONFINITE : SWE_OK;
+    }
+    return bad ? SWE_ENONFINITE : SWE_OK;
+}
+
+int scenario_read(const DevScenario &d, hipStream_t stream, float *h, float *hu, float *hv,
+                  swe_stats *st)
+{
+    const Geo &g = d.geo;
+    const size_t row = (size_t)g.nx * sizeof(float), spitch = (size_t)g.pitch * sizeof(float);
+    float *outs[3] = {h, hu, hv};
+    for (int c = 0; c < 3; ++c)
+        if (outs[c])
+            SWE_HIP_TRY(hipMemcpy2DAsync(outs[c], row, g.U[c], spitch, row, g.ny, hipMemcpyDefault, stream));
+    int rc = launch_mass(g, stream);
+    if (rc) return rc;
+    DevScen ds;
+    SWE_HIP_TRY(hipMemcpyAsync(&ds, g.sd, sizeof ds, hipMemcpyDeviceToHost, stream));
+    SWE_HIP_TRY(hipStreamSynchronize(stream));
+    return stats_from_dev(g, ds, st);
+}
+
+}  // namespace swe
+
+// ---------------------------------------------------------------------------
+// single-scenario context (C ABI)
+// ---------------------------------------------------------------------------
+using namespace swe;
+
+struct swe_ctx {
+    swe_params p{};
+    DevScenario d;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    int tile = -1;        // -1: automatic
+    int graph_steps = 32;
+    hipGraphExec_t graph = nullptr;
+    int graph_k = 0;
+    int graph_tile = -1;
+};
+
+static int ctx_tile(const swe_ctx *c)
+{
+    return c->tile >= 0 ? c->tile : default_variant(c->p.nx, c->p.ny);
+}
+
+static int enqueue_steps(swe_ctx *c, int n)
+{
+    const Variant &v = variant(ctx_tile(c));
+    for (int s = 0; s < n; ++s)
+        for (int st = 1; st <= 3; ++st) {
+            const int rc = launch_stage(v, st, c->d.geo, c->stream);
+            if (rc) return rc;
+        }
+    return SWE_OK;
+}
+
+static void drop_graph(swe_ctx *c)
+{
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+    c->graph_k = 0;
+}
+
+static int build_graph(swe_ctx *c, int k)
+{
+    drop_graph(c);
+    hipGraph_t g = nullptr;
+    SWE_HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_steps(c, k);
+    const hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (rc || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : SWE_EDEVICE;
+    }
+    const hipError_t ie = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+        c->graph = nullptr;
+        return SWE_EDEVICE;
+    }
+    c->graph_k = k;
+    c->graph_tile = ctx_tile(c);
+    return SWE_OK;
+}
+
+extern "C" {
+
+int swe_create(const swe_params *p, const float *b, const float *manning_n, const float *h0,
+               const float *hu0, const float *hv0, void *hip_stream, swe_ctx **out)
+{
+    if (!out) return SWE_EINVAL;
+    *out = nullptr;
+    HostFields f;
+    int rc = load_fields(p, b, manning_n, h0, hu0, hv0, f);
+    if (rc) return rc;
+    swe_ctx *c = new (std::nothrow) swe_ctx();
+    if (!c) return SWE_ENOMEM;
+    c->p = *p;
+    (void)hipGetDevice(&c->device);
+    if (hip_stream) {
+        c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return SWE_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    rc = scenario_upload(*p, f, c->stream, c->d);
+    if (rc) {
+        swe_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return SWE_OK;
+}
+
+int swe_step(swe_ctx *c, int32_t nsteps)
+{
+    if (!c || nsteps < 0) return SWE_EINVAL;
+    int n = nsteps;
+    if (c->graph_steps > 0 && n >= c->graph_steps) {
+        if (!c->graph || c->graph_k != c->graph_steps || c->graph_tile != ctx_tile(c)) {
+            const int rc = build_graph(c, c->graph_steps);
+            if (rc) return rc;
+        }
+        while (n >= c->graph_k) {
+            SWE_HIP_TRY(hipGraphLaunch(c->graph, c->stream));
+            n -= c->graph_k;
+        }
+    }
+    return enqueue_steps(c, n);
+}
+
+int swe_read(swe_ctx *c, float *h, float *hu, float *hv, swe_stats *st)
+{
+    if (!c) return SWE_EINVAL;
+    return scenario_read(c->d, c->stream, h, hu, hv, st);
+}
+
+void swe_destroy(swe_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graph(c);
+    scenario_free(c->d);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int swe_set_option(swe_ctx *c, int32_t key, int64_t value)
+{
+    if (!c) return SWE_EINVAL;
+    if (key == SWE_OPT_GRAPH_STEPS) {
+        if (value < 0 || value > 100000) return SWE_EINVAL;
+        c->graph_steps = (int)value;
+        drop_graph(c);
+        return SWE_OK;
+    }
+    if (key == SWE_OPT_TILE) {
+        if (value < -1 || value >= variant_count()) return SWE_EINVAL;
+        c->tile = (int)value;
+        drop_graph(c);
+        return SWE_OK;
+    }
+    return SWE_EINVAL;
+}
+
+int swe_state_device(swe_ctx *c, float **h, float **hu, float **hv, int64_t *pitch)
+{
+    if (!c) return SWE_EINVAL;
+    if (h) *h = c->d.geo.U[0];
+    if (hu) *hu = c->d.geo.U[1];
+    if (hv) *hv = c->d.geo.U[2];
+    if (pitch) *pitch = c->d.geo.pitch;
+    return SWE_OK;
+}
+
+int swe_time_stages(swe_ctx *c, int32_t nsteps, double *ms)
+{
+    if (!c || nsteps <= 0 || !ms) return SWE_EINVAL;
+    hipEvent_t ev[6];
+    for (int k = 0; k < 6; ++k)
+        if (hipEventCreate(&ev[k]) != hipSuccess) {
+            for (int q = 0; q < k; ++q) (void)hipEventDestroy(ev[q]);
+            return SWE_EDEVICE;
+        }
+    double acc[3] = {0, 0, 0};
+    int rc = SWE_OK;
+    const Variant &v = variant(ctx_tile(c));
+    for (int s = 0; s < nsteps && !rc; ++s) {
+        for (int st = 0; st < 3 && !rc; ++st) {
+            if (hipEventRecord(ev[2 * st], c->stream) != hipSuccess) rc = SWE_EDEVICE;
+            if (!rc) rc = launch_stage(v, st + 1, c->d.geo, c->stream);
+            if (!rc && hipEventRecord(ev[2 * st + 1], c->stream) != hipSuccess) rc = SWE_EDEVICE;
+        }
+        if (!rc && hipEventSynchronize(ev[5]) != hipSuccess) rc = SWE_EDEVICE;
+        for (int st = 0; st < 3 && !rc; ++st) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, ev[2 * st], ev[2 * st + 1]) != hipSuccess) rc = SWE_EDEVICE;
+            acc[st] += t;
+        }
+    }
+    for (int k = 0; k < 6; ++k) (void)hipEventDestroy(ev[k]);
+    for (int st = 0; st < 3; ++st) ms[st] = acc[st] / nsteps;
+    return rc;
+}
+
+int swe_tile_count(void) { return variant_count(); }
+
+int swe_tile_info(int32_t index, int32_t *tx, int32_t *ty, int32_t *r, int32_t *threads)
+{
+    if (index < 0 || index >= variant_count()) return SWE_ENOTFOUND;
+    const Variant &v = variant(index);
+    if (tx) *tx = v.tx;
+    if (ty) *ty = v.ty;
+    if (r) *r = v.r;
+    if (threads) *threads = v.nt;
+    return SWE_OK;
+}
+
+size_t swe_footprint(int32_t nx, int32_t ny)
+{
+    if (nx < 1 || ny < 1) return 0;
+    return scenario_bytes(nx, ny);
+}
+
+const char *swe_strerror(int code)
+{
+    switch (code) {
+    case SWE_OK: return "ok";
+    case SWE_EINVAL: return "invalid argument";
+    case SWE_ENOMEM: return "out of device memory or over the memory budget";
+    case SWE_EDEVICE: return "HIP runtime error";
+    case SWE_ENONFINITE: return "non-finite wave speed (state poisoned)";
+    case SWE_EBUSY: return "request queue full";
+    case SWE_ENOTFOUND: return "unknown ticket or index";
+    default: return "unknown error";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// swe_internal.hpp - host-side pieces shared by the single-scenario context,
+// the batched launcher and the server: validation, frozen ghosts, device
+// scenario storage and the tile-variant registry.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/swe.h"
+#include "swe_stage.hpp"
+
+namespace swe {
+
+#define SWE_HIP_TRY(expr)                       \
+    do {                                        \
+        if ((expr) != hipSuccess) return SWE_EDEVICE; \
+    } while (0)
+
+// Host copy of a scenario's inputs (validated).
+struct HostFields {
+    int nx = 0, ny = 0;
+    std::vector<float> b, n, h, hu, hv;
+};
+
+int validate_params(const swe_params *p);
+
+// Copies the five fields (host or device pointers) and validates them.
+int load_fields(const swe_params *p, const float *b, const float *n, const float *h,
+                const float *hu, const float *hv, HostFields &out);
+
+// Row pitch (elements) of every plane: nx rounded up to 64 floats.
+inline int plane_pitch(int nx) { return (nx + 63) / 64 * 64; }
+
+// Frozen FIXED ghosts (see ghost_index in swe_stage.hpp): (h, hu, hv) of the
+// nearest interior cell, b extended linearly from the two nearest cells.
+std::vector<float> build_ghosts(const swe_params &p, const HostFields &f);
+
+// Device storage of one scenario: 11 planes + ghosts + DevScen in one block.
+struct DevScenario {
+    void *base = nullptr;
+    size_t bytes = 0;
+    Geo geo{};
+};
+
+size_t scenario_bytes(int nx, int ny);
+
+// Allocates (hipMalloc) and uploads on `stream`, then runs the init kernel.
+int scenario_upload(const swe_params &p, const HostFields &f, hipStream_t stream, DevScenario &d);
+// Uploads into caller-provided device memory of scenario_bytes() size.
+int scenario_upload_into(void *mem, const swe_params &p, const HostFields &f, hipStream_t stream,
+                         DevScenario &d);
+void scenario_free(DevScenario &d);
+
+// Wave speeds of u^n into DevScen slot 0 and the initial runup (after a
+// zeroing of DevScen).
+int launch_init(const Geo &g, hipStream_t stream);
+// Deterministic FP64 sum of h into DevScen::mass_sum.
+int launch_mass(const Geo &g, hipStream_t stream);
+
+// Reads state planes (any may be NULL; host or device) and the diagnostics.
+int scenario_read(const DevScenario &d, hipStream_t stream, float *h, float *hu, float *hv,
+                  swe_stats *st);
+int stats_from_dev(const Geo &g, const DevScen &ds, swe_stats *st);
+
+// ---- tile variants -------------------------------------------------------
+struct Variant {
+    int tx, ty, r, nt;
+    size_t lds_bytes;
+    void (*stage[3])(Geo, int, int);  // single-scenario stage kernels
+};
+int variant_count();
+const Variant &variant(int i);
+int default_variant(int nx, int ny);
+int launch_stage(const Variant &v, int stage, const Geo &g, hipStream_t stream);
+
+double now_seconds();
+
+// Builds the round/ticket tables of one run over `geos` (scenario i advances
+// ksteps[i] >= 0 steps) and launches it on `stream` with tile variant vi, in
+// SWE_BATCH_PERSISTENT or SWE_BATCH_ROUNDS mode, optionally as a hipGraph.
+// Asynchronous; the tables stay valid until the next run (which first waits
+// for `stream`).
+struct SegmentLauncher {
+    void *dmem = nullptr;
+    size_t dbytes = 0;
+    std::vector<char> hbuf;
+    hipGraphExec_t graph = nullptr;
+    int cus = 0;
+    int group = 4;  // tickets taken per atomic in persistent mode
+    ~SegmentLauncher();
+    int run(const std::vector<Geo> &geos, const std::vector<int> &ksteps, int vi, int mode, bool use_graph,
+            hipStream_t stream);
+};
+
+}  // namespace swe

@@ -1,0 +1,410 @@
+// swe_server.hip - continuous batching of scenario requests.
+//
+// A host thread owns a device arena of the memory budget.  Requests wait in a
+// FIFO queue; a request is admitted when a slot is free and its footprint
+// (swe_footprint) fits a first-fit hole of the arena, so admission is by HBM
+// footprint and never calls hipMalloc or hipFree.  Resident scenarios advance
+// together in segments: one persistent launch advances every resident
+// scenario by min(segment_steps, its remaining steps).  While a segment runs,
+// the thread uploads newly admitted requests on a copy stream and copies the
+// results of scenarios finished in the previous segment back to host memory;
+// those scenarios then leave the arena.  Requests that arrive while others are
+// on the GPU therefore join the mix at the next segment boundary, and their
+// work overlaps with that of the requests already running.  Every scenario
+// runs the same per-tile stage code as alone, so its result does not depend
+// on what else is in the mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "swe_internal.hpp"
+
+namespace swe {
+
+// First-fit allocator over one device block; offsets aligned to 256 bytes.
+class Arena {
+  public:
+    int init(size_t bytes)
+    {
+        bytes_ = bytes / 256 * 256;
+        if (hipMalloc(&base_, bytes_) != hipSuccess) {
+            (void)hipGetLastError();
+            base_ = nullptr;
+            return SWE_ENOMEM;
+        }
+        free_[0] = bytes_;
+        return SWE_OK;
+    }
+    ~Arena()
+    {
+        if (base_) (void)hipFree(base_);
+    }
+    void *alloc(size_t n)
+    {
+        n = (n + 255) / 256 * 256;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                const size_t off = it->first, len = it->second;
+                free_.erase(it);
+                if (len > n) free_[off + n] = len - n;
+                used_ += n;
+                high_ = std::max(high_, used_);
+                return static_cast<char *>(base_) + off;
+            }
+        }
+        return nullptr;
+    }
+    void release(void *p, size_t n)
+    {
+        n = (n + 255) / 256 * 256;
+        size_t off = static_cast<char *>(p) - static_cast<char *>(base_);
+        used_ -= n;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + n == next->first) {
+            n += next->second;
+            free_.erase(next);
+        }
+        auto prev = free_.lower_bound(off);
+        if (prev != free_.begin()) {
+            --prev;
+            if (prev->first + prev->second == off) {
+                prev->second += n;
+                return;
+            }
+        }
+        free_[off] = n;
+    }
+    size_t capacity() const { return bytes_; }
+    size_t used() const { return used_; }
+    size_t high_water() const { return high_; }
+
+  private:
+    void *base_ = nullptr;
+    size_t bytes_ = 0, used_ = 0, high_ = 0;
+    std::map<size_t, size_t> free_;  // offset -> length
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    swe_params p{};
+    HostFields f;
+    int nsteps = 0;
+    int status = SWE_PENDING;
+    int error = SWE_OK;
+    bool cancel = false;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    // resident state
+    DevScenario d;
+    int done_steps = 0;
+    // result
+    swe_stats st{};
+    std::vector<float> h, hu, hv;
+};
+
+}  // namespace swe
+
+using namespace swe;
+
+struct swe_server {
+    int device = 0;
+    int max_slots = 64;
+    int segment_steps = 100;
+    size_t max_queue = 1 << 16;
+    Arena arena;
+    hipStream_t compute = nullptr, copy = nullptr;
+    SegmentLauncher seg;
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    std::deque<Request *> queue;
+    std::vector<Request *> active;
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+    int64_t submitted = 0, completed = 0, failed = 0, cancelled = 0, segments = 0;
+    int fatal = SWE_OK;
+
+    void loop();
+    int admit_locked(std::vector<Request *> &admitted);
+    void finish(Request *r, int status, int error);
+};
+
+void swe_server::finish(Request *r, int status, int error)
+{
+    r->status = status;
+    r->error = error;
+    r->t_done = now_seconds();
+    if (status == SWE_DONE) ++completed;
+    else if (status == SWE_CANCELLED) ++cancelled;
+    else ++failed;
+}
+
+// Moves queued requests that fit into the arena; caller holds `mu`.
+int swe_server::admit_locked(std::vector<Request *> &admitted)
+{
+    while (!queue.empty() && (int)(active.size() + admitted.size()) < max_slots) {
+        Request *r = queue.front();
+        if (r->cancel) {
+            queue.pop_front();
+            r->f = HostFields();
+            finish(r, SWE_CANCELLED, SWE_OK);
+            continue;
+        }
+        void *mem = arena.alloc(scenario_bytes(r->p.nx, r->p.ny));
+        if (!mem) break;  // FIFO: wait for memory to free up
+        queue.pop_front();
+        r->d.base = mem;
+        r->t_admit = now_seconds();
+        admitted.push_back(r);
+    }
+    return SWE_OK;
+}
+
+void swe_server::loop()
+{
+    (void)hipSetDevice(device);
+    std::vector<Request *> retiring;  // finished in the previous segment, results not yet copied
+    for (;;) {
+        std::vector<Request *> admitted;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            if (stop) break;
+            admit_locked(admitted);
+            if (active.empty() && admitted.empty() && retiring.empty()) {
+                cv.wait_for(lk, std::chrono::milliseconds(20));
+                continue;
+            }
+        }
+        // upload admitted requests (copy stream) and make them resident
+        for (Request *r : admitted) {
+            const int rc = scenario_upload_into(r->d.base, r->p, r->f, copy, r->d);
+            std::lock_guard<std::mutex> lk(mu);
+            r->f = HostFields();
+            if (rc) {
+                arena.release(r->d.base, scenario_bytes(r->p.nx, r->p.ny));
+                r->d.base = nullptr;
+                finish(r, SWE_FAILED, rc);
+            } else {
+                active.push_back(r);
+            }
+        }
+        // one segment over every resident scenario with steps left
+        std::vector<Geo> geos;
+        std::vector<int> ks;
+        std::vector<Request *> in_seg;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (Request *r : active) {
+                if (r->cancel || r->done_steps >= r->nsteps) continue;
+                geos.push_back(r->d.geo);
+                ks.push_back(std::min(segment_steps, r->nsteps - r->done_steps));
+                in_seg.push_back(r);
+            }
+        }
+        int rc = SWE_OK;
+        if (!in_seg.empty()) {
+            int big = 0;
+            for (size_t i = 1; i < geos.size(); ++i)
+                if ((size_t)geos[i].nx * geos[i].ny > (size_t)geos[big].nx * geos[big].ny) big = (int)i;
+            rc = seg.run(geos, ks, default_variant(geos[big].nx, geos[big].ny), SWE_BATCH_PERSISTENT, false,
+                         compute);
+            std::lock_guard<std::mutex> lk(mu);
+            ++segments;
+            if (rc) fatal = rc;
+        }
+        // while the segment runs: results of the previous segment's finishers
+        for (Request *r : retiring) {
+            int rrc = SWE_OK;
+            if (!r->cancel) {
+                const size_t N = (size_t)r->p.nx * r->p.ny;
+                r->h.resize(N);
+                r->hu.resize(N);
+                r->hv.resize(N);
+                rrc = scenario_read(r->d, copy, r->h.data(), r->hu.data(), r->hv.data(), &r->st);
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            arena.release(r->d.base, scenario_bytes(r->p.nx, r->p.ny));
+            r->d.base = nullptr;
+            if (r->cancel) finish(r, SWE_CANCELLED, SWE_OK);
+            else if (rrc == SWE_OK) finish(r, SWE_DONE, SWE_OK);
+            else finish(r, SWE_FAILED, rrc);
+        }
+        retiring.clear();
+        if (hipStreamSynchronize(compute) != hipSuccess) rc = SWE_EDEVICE;
+        // account the segment, detect failures, pick the finishers
+        std::vector<DevScen> ds(in_seg.size());
+        for (size_t i = 0; i < in_seg.size(); ++i)
+            (void)hipMemcpyAsync(&ds[i], in_seg[i]->d.geo.sd, sizeof(DevScen), hipMemcpyDeviceToHost, copy);
+        (void)hipStreamSynchronize(copy);
+        std::lock_guard<std::mutex> lk(mu);
+        for (size_t i = 0; i < in_seg.size(); ++i) {
+            in_seg[i]->done_steps += ks[i];
+            if (rc) in_seg[i]->error = rc;
+        }
+        std::vector<Request *> keep;
+        for (Request *r : active) {
+            bool out = r->cancel || r->done_steps >= r->nsteps || rc != SWE_OK;
+            for (size_t i = 0; i < in_seg.size(); ++i)
+                if (in_seg[i] == r && ((ds[i].flags & 1u) || ds[i].alpha[0][0] >= 0x7f800000u)) {
+                    r->error = SWE_ENONFINITE;
+                    out = true;
+                }
+            if (out) {
+                if (r->error != SWE_OK && !r->cancel) {
+                    arena.release(r->d.base, scenario_bytes(r->p.nx, r->p.ny));
+                    r->d.base = nullptr;
+                    finish(r, SWE_FAILED, r->error);
+                } else {
+                    retiring.push_back(r);
+                }
+            } else {
+                keep.push_back(r);
+            }
+        }
+        active.swap(keep);
+    }
+    // shutdown: drop whatever is resident
+    (void)hipStreamSynchronize(compute);
+    (void)hipStreamSynchronize(copy);
+}
+
+extern "C" {
+
+int swe_server_create(int32_t device, size_t mem_budget, int32_t max_slots, int32_t segment_steps,
+                      swe_server **out)
+{
+    if (!out || max_slots <= 0 || segment_steps <= 0) return SWE_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SWE_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return SWE_EDEVICE;
+    if (mem_budget == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) return SWE_EDEVICE;
+        mem_budget = fr / 2;
+    }
+    swe_server *sv = new (std::nothrow) swe_server();
+    if (!sv) return SWE_ENOMEM;
+    sv->device = device;
+    sv->max_slots = max_slots;
+    sv->segment_steps = segment_steps;
+    int rc = sv->arena.init(mem_budget);
+    if (rc) {
+        delete sv;
+        return rc;
+    }
+    if (hipStreamCreateWithFlags(&sv->compute, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&sv->copy, hipStreamNonBlocking) != hipSuccess) {
+        if (sv->compute) (void)hipStreamDestroy(sv->compute);
+        delete sv;
+        return SWE_EDEVICE;
+    }
+    sv->th = std::thread([sv] { sv->loop(); });
+    *out = sv;
+    return SWE_OK;
+}
+
+int swe_submit(swe_server *sv, const swe_params *p, const float *b, const float *n, const float *h0,
+               const float *hu0, const float *hv0, int32_t nsteps, uint64_t *ticket)
+{
+    if (!sv || !ticket || nsteps < 0) return SWE_EINVAL;
+    auto r = std::make_unique<Request>();
+    int rc = load_fields(p, b, n, h0, hu0, hv0, r->f);
+    if (rc) return rc;
+    if (scenario_bytes(p->nx, p->ny) > sv->arena.capacity()) return SWE_ENOMEM;
+    r->p = *p;
+    r->nsteps = nsteps;
+    r->t_submit = now_seconds();
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->queue.size() >= sv->max_queue) return SWE_EBUSY;
+    r->ticket = sv->next_ticket++;
+    *ticket = r->ticket;
+    sv->queue.push_back(r.get());
+    sv->reqs[r->ticket] = std::move(r);
+    ++sv->submitted;
+    sv->cv.notify_one();
+    return SWE_OK;
+}
+
+int swe_poll(swe_server *sv, uint64_t ticket, swe_result *res, float *h, float *hu, float *hv)
+{
+    if (!sv || !res) return SWE_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end()) return SWE_ENOTFOUND;
+    Request *r = it->second.get();
+    std::memset(res, 0, sizeof *res);
+    res->status = r->status;
+    res->error = r->error;
+    res->t_submit = r->t_submit;
+    res->t_admit = r->t_admit;
+    res->t_done = r->t_done;
+    if (r->status == SWE_PENDING) return SWE_OK;
+    if (r->status == SWE_DONE) {
+        res->t = r->st.t;
+        res->mass = r->st.mass;
+        res->runup = r->st.runup;
+        res->steps = r->st.step;
+        const size_t N = r->h.size();
+        if (h) std::memcpy(h, r->h.data(), N * sizeof(float));
+        if (hu) std::memcpy(hu, r->hu.data(), N * sizeof(float));
+        if (hv) std::memcpy(hv, r->hv.data(), N * sizeof(float));
+    }
+    sv->reqs.erase(it);  // a final status is reported once
+    return SWE_OK;
+}
+
+int swe_cancel(swe_server *sv, uint64_t ticket)
+{
+    if (!sv) return SWE_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end()) return SWE_ENOTFOUND;
+    it->second->cancel = true;
+    sv->cv.notify_one();
+    return SWE_OK;
+}
+
+int swe_server_get_stats(swe_server *sv, swe_server_stats *st)
+{
+    if (!sv || !st) return SWE_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    st->submitted = sv->submitted;
+    st->completed = sv->completed;
+    st->failed = sv->failed;
+    st->cancelled = sv->cancelled;
+    st->queued = (int64_t)sv->queue.size();
+    st->active = (int64_t)sv->active.size();
+    st->mem_in_use = sv->arena.used();
+    st->mem_high_water = sv->arena.high_water();
+    st->mem_budget = sv->arena.capacity();
+    st->segments = sv->segments;
+    return sv->fatal;
+}
+
+void swe_server_destroy(swe_server *sv)
+{
+    if (!sv) return;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv.notify_all();
+    if (sv->th.joinable()) sv->th.join();
+    (void)hipStreamDestroy(sv->compute);
+    (void)hipStreamDestroy(sv->copy);
+    delete sv;
+}
+
+}  // extern "C"

@@ -1,0 +1,558 @@
+// swe_stage.hpp - device code of one TVD-RK3 stage on one tile (gfx950).
+//
+// One stage computes out = a_n u^n + a_w (w + dt L(w)) (Methods, Eq. (8)) for
+// every cell of a TX x TY tile, where L is the explicit operator of Eq. (7):
+// the divergence of WENO5-reconstructed Lax-Friedrichs split fluxes
+// (Methods, WENO and Lax-Friedrichs paragraphs) plus the cell-centred bed and
+// Manning sources of Eqs. (2)-(3).
+//
+// Work layout, per block:
+//   1. the tile's input state (h, hu, hv, b) with a 3-cell cross-shaped halo
+//      is staged in LDS with coalesced row loads; ghosts are mirrored or read
+//      from frozen planes on the fly, so no separate ghost pass exists;
+//   2. x sweep: each thread walks R consecutive cells of one row, keeping a
+//      3-cell window of split fluxes in registers.  Every cell centre's
+//      second and first differences, the three smoothness indicators and the
+//      four stencil polynomials are computed once and shared by the three
+//      faces that use them; a face's WENO sums complete two centres later.
+//      The x part of L goes to LDS;
+//   3. y sweep: the same along columns, then friction, the RK combination,
+//      the wet/dry fix-up, the store, and the epilogue reductions (wave
+//      shuffles -> LDS -> at most one atomic per block and quantity) of the
+//      next stage's wave speeds, the clamped mass and the runup.  The FP64
+//      mass is not on the step path: a separate deterministic reduction
+//      computes it when the state is read.
+// The arithmetic of a cell does not depend on the tile shape or on which
+// launch runs the tile, so every tile variant and launch mode gives bitwise
+// identical states.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace swe {
+
+constexpr int HALO = 3;
+constexpr int BC_REFLECT = 0;
+constexpr int BC_FIXED = 1;
+constexpr int MASS_BLOCKS = 256;
+
+// Per-scenario device scalars.  alpha[s] holds the float bits of the wave
+// speeds of the input of stage s+1 (slot 0: u^n, 1: u^(1), 2: u^(2)).
+struct alignas(64) DevScen {
+    unsigned int alpha[3][2];
+    float dt;              // step size of the step in flight (written by stage 1)
+    unsigned int runup;    // float bits of the running max runup elevation
+    unsigned int flags;    // bit 0: non-finite state seen
+    unsigned int pad0;
+    double t;              // simulated time (FP64)
+    long long step;        // completed steps
+    double mass_sum;       // sum of h over the grid (x dx dy), refreshed by the mass kernel
+    double clamp_sum;      // weighted sum of clamped depth deficits (x dx dy on read)
+    double pad1[2];
+};
+
+// Geometry, parameters and buffers of one scenario.
+struct Geo {
+    int nx, ny, pitch;       // pitch: row stride of every plane (elements)
+    int bc[4];               // west, east, south, north
+    float dx, dy, inv_dx, inv_dy;
+    float g, half_g, h_dry, eps12;  // eps12 = 12 * weno_eps (indicators are kept x12)
+    float kappa_cap, cfl, dt_fixed;
+    int pad;
+    const float *b, *gn2;    // bed and g n^2 planes
+    float *U[3], *A[3], *B[3];      // u^n, u^(1), u^(2): h, hu, hv planes
+    const float *ghost;      // frozen FIXED ghosts, see ghost_index()
+    DevScen *sd;
+    double *mass_part;       // MASS_BLOCKS partial sums of the mass kernel
+};
+
+// Frozen ghosts of a FIXED side: [field h,hu,hv,b][layer 0..2][position along the side].
+// West/east sides have length ny and start at 0 and 12*ny; south/north have
+// length nx and start at 24*ny and 24*ny + 12*nx.
+__device__ __forceinline__ int ghost_index(const Geo &G, int side, int field, int layer, int pos)
+{
+    const int len = side < 2 ? G.ny : G.nx;
+    const int base = side == 0 ? 0 : side == 1 ? 12 * G.ny : side == 2 ? 24 * G.ny : 24 * G.ny + 12 * G.nx;
+    return base + (field * 3 + layer) * len + pos;
+}
+
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+template <int TX_, int TY_, int R_>
+struct TileCfg {
+    static constexpr int TX = TX_, TY = TY_, R = R_;
+    static constexpr int NT = TX * TY / R;         // threads per block
+    static constexpr int WX = TX + 2 * HALO;       // staged columns
+    static constexpr int WY = TY + 2 * HALO;       // staged rows
+    static constexpr int SX = WX + 1;              // odd LDS row stride
+    static constexpr int PLANE = SX * WY;
+    static constexpr int XR = TX + 1;              // row stride of the x-sweep results
+    static constexpr int XPLANE = XR * TY;
+    static constexpr int LDS_FLOATS = 4 * PLANE + 3 * XPLANE;
+    static_assert(TX % R == 0 && TY % R == 0, "R must divide the tile");
+    static_assert(NT % 64 == 0, "whole wavefronts");
+};
+
+// Sweep constants shared by the x and y sweeps.
+struct SweepK {
+    float ha;       // alpha / 2 of the sweep direction
+    float inv_ds;   // 1/dx or 1/dy
+    float g, half_g, h_dry;
+    float e0, e1, e2;  // 12 eps / sqrt(d_k)
+};
+
+// WENO5 linear weights d = (1/10, 6/10, 3/10) enter as 1/sqrt(d_k): the
+// unnormalised weight d_k / (eps + beta_k)^2 is computed as 1/t^2 with
+// t = (eps + beta_k) / sqrt(d_k).
+constexpr float KD0 = 3.16227766016838f;  // 1/sqrt(0.1)
+constexpr float KD1 = 1.29099444873581f;  // 1/sqrt(0.6)
+constexpr float KD2 = 1.82574185835055f;  // 1/sqrt(0.3)
+
+__device__ __forceinline__ float wt(float beta12, float kd, float ek)
+{
+    const float r = frcp(fmaf(beta12, kd, ek));
+    return r * r;
+}
+
+// One sweep along x (DIR 0) or y (DIR 1) over R cells.  li0 is the LDS index
+// of the window cell 3 before the first cell, st the LDS step between cells.
+// res[k][m] receives the sweep's part of L for cell k: -(Fhat_{k+1/2} -
+// Fhat_{k-1/2})/ds, plus the bed term -g (h+b)(bhat_{k+1/2} - bhat_{k-1/2})/ds
+// on the momentum component normal to the faces.
+template <int R, int DIR>
+__device__ __forceinline__ void sweep(const float *__restrict__ Lh, const float *__restrict__ Lhu,
+                                      const float *__restrict__ Lhv, const float *__restrict__ Lb,
+                                      int li0, int st, const SweepK &K, float res[R][3])
+{
+    constexpr int NF = R + 1;                 // faces k-1/2 for k = 0..R
+    constexpr int MB = DIR == 0 ? 1 : 2;      // component whose weights reconstruct b
+    float np_[NF][3], dp_[NF][3], nm_[NF][3], dm_[NF][3], nbp[NF], nbm[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) np_[f][m] = dp_[f][m] = nm_[f][m] = dm_[f][m] = 0.f;
+        nbp[f] = nbm[f] = 0.f;
+    }
+    float win[3][7];   // rolling window: F+ (3), F- (3), b
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int q = 0; q < 7; ++q) win[s][q] = 0.f;
+    float eta[R];
+    float fprev[3] = {0.f, 0.f, 0.f}, bprev = 0.f;
+
+#pragma unroll
+    for (int w = -HALO; w < R + HALO; ++w) {
+        const int li = li0 + (w + HALO) * st;
+        const float h = Lh[li], hu = Lhu[li], hv = Lhv[li], b = Lb[li];
+        // cell flux, LF split vector u~ = (h+b, hu, hv) and the split fluxes
+        const float inv = h > K.h_dry ? frcp(h) : 0.f;
+        const float e = h + b;
+        const float pres = K.half_g * (h - b) * e;
+        float F0, F1, F2;
+        if (DIR == 0) {
+            F0 = hu;
+            F1 = fmaf(hu, hu * inv, pres);
+            F2 = hu * (hv * inv);
+        } else {
+            F0 = hv;
+            F1 = hv * (hu * inv);
+            F2 = fmaf(hv, hv * inv, pres);
+        }
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            win[0][q] = win[1][q];
+            win[1][q] = win[2][q];
+        }
+        win[2][0] = fmaf(K.ha, e, 0.5f * F0);
+        win[2][1] = fmaf(K.ha, hu, 0.5f * F1);
+        win[2][2] = fmaf(K.ha, hv, 0.5f * F2);
+        win[2][3] = fmaf(-K.ha, e, 0.5f * F0);
+        win[2][4] = fmaf(-K.ha, hu, 0.5f * F1);
+        win[2][5] = fmaf(-K.ha, hv, 0.5f * F2);
+        win[2][6] = b;
+        if (w >= 0 && w < R) eta[w >= 0 && w < R ? w : 0] = e;
+        if (w < -1) continue;
+
+        const int c = w - 1;  // cell centre whose three cells are now in the window
+        // stencil polynomials of b at this centre (shared by both directions)
+        float bRR, bR, bL, bLL;
+        {
+            const float D = fmaf(-2.f, win[1][6], win[0][6] + win[2][6]);
+            const float E = win[2][6] - win[0][6];
+            const float t0 = fmaf(D, 1.f / 12.f, win[1][6]);
+            const float t1 = t0 + D;
+            bR = fmaf(E, 0.25f, t0);
+            bL = fmaf(E, -0.25f, t0);
+            bRR = fmaf(E, 0.75f, t1);
+            bLL = fmaf(E, -0.75f, t1);
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const float vm = win[0][q], v0 = win[1][q], vp = win[2][q];
+            const float D = fmaf(-2.f, v0, vm + vp);
+            const float E = vp - vm;
+            const float base = (13.f * D) * D;
+            const float sR = fmaf(2.f, D, E);
+            const float sL = fmaf(2.f, D, -E);
+            const float bM_ = fmaf(3.f * E, E, base);     // 12 x indicator, centred stencil
+            const float bR_ = fmaf(3.f * sR, sR, base);   // stencil whose right end is the face side
+            const float bL_ = fmaf(3.f * sL, sL, base);
+            const float t0 = fmaf(D, 1.f / 12.f, v0);
+            const float pR = fmaf(E, 0.25f, t0);          // value at c + 1/2
+            const float pL = fmaf(E, -0.25f, t0);         // value at c - 1/2
+            if (q < 3) {
+                const int m = q;
+                // R+ at face f (index f <-> face f-1/2): roles 0, 1, 2 from centres f-2, f-1, f
+                const float pRR = fmaf(E, 0.75f, t0 + D); // value at c + 3/2
+                if (c + 2 >= 0 && c + 2 <= R) {
+                    const int f = (c + 2 >= 0 && c + 2 <= R) ? c + 2 : 0;
+                    const float a = wt(bR_, KD0, K.e0);
+                    np_[f][m] = fmaf(a, pRR, np_[f][m]);
+                    dp_[f][m] += a;
+                    if (m == MB) nbp[f] = fmaf(a, bRR, nbp[f]);
+                }
+                if (c + 1 >= 0 && c + 1 <= R) {
+                    const int f = (c + 1 >= 0 && c + 1 <= R) ? c + 1 : 0;
+                    const float a = wt(bM_, KD1, K.e1);
+                    np_[f][m] = fmaf(a, pR, np_[f][m]);
+                    dp_[f][m] += a;
+                    if (m == MB) nbp[f] = fmaf(a, bR, nbp[f]);
+                }
+                if (c >= 0 && c <= R) {
+                    const int f = (c >= 0 && c <= R) ? c : 0;
+                    const float a = wt(bL_, KD2, K.e2);
+                    np_[f][m] = fmaf(a, pL, np_[f][m]);
+                    dp_[f][m] += a;
+                    if (m == MB) nbp[f] = fmaf(a, bL, nbp[f]);
+                }
+            } else {
+                const int m = q - 3;
+                // R- at face f: roles 0, 1, 2 from centres f+1, f, f-1 (mirrored stencil)
+                const float pLL = fmaf(E, -0.75f, t0 + D); // value at c - 3/2
+                if (c - 1 >= 0 && c - 1 <= R) {
+                    const int f = (c - 1 >= 0 && c - 1 <= R) ? c - 1 : 0;
+                    const float a = wt(bL_, KD0, K.e0);
+                    nm_[f][m] = fmaf(a, pLL, nm_[f][m]);
+                    dm_[f][m] += a;
+                    if (m == MB) nbm[f] = fmaf(a, bLL, nbm[f]);
+                }
+                if (c >= 0 && c <= R) {
+                    const int f = (c >= 0 && c <= R) ? c : 0;
+                    const float a = wt(bM_, KD1, K.e1);
+                    nm_[f][m] = fmaf(a, pL, nm_[f][m]);
+                    dm_[f][m] += a;
+                    if (m == MB) nbm[f] = fmaf(a, bL, nbm[f]);
+                }
+                if (c + 1 >= 0 && c + 1 <= R) {
+                    const int f = (c + 1 >= 0 && c + 1 <= R) ? c + 1 : 0;
+                    const float a = wt(bR_, KD2, K.e2);
+                    nm_[f][m] = fmaf(a, pR, nm_[f][m]);
+                    dm_[f][m] += a;
+                    if (m == MB) nbm[f] = fmaf(a, bR, nbm[f]);
+                }
+            }
+        }
+        // face c-1 has received all six contributions
+        if (c - 1 >= 0 && c - 1 <= R) {
+            const int f = (c - 1 >= 0 && c - 1 <= R) ? c - 1 : 0;
+            float Fh[3], rp_b = 0.f, rm_b = 0.f;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const float rp = frcp(dp_[f][m]);
+                const float rm = frcp(dm_[f][m]);
+                Fh[m] = fmaf(np_[f][m], rp, nm_[f][m] * rm);
+                if (m == MB) {
+                    rp_b = rp;
+                    rm_b = rm;
+                }
+            }
+            const float bh = 0.5f * fmaf(nbp[f], rp_b, nbm[f] * rm_b);
+            if (f >= 1) {
+                const int k = f - 1;
+#pragma unroll
+                for (int m = 0; m < 3; ++m) res[k][m] = (fprev[m] - Fh[m]) * K.inv_ds;
+                res[k][MB] = fmaf(-K.g * eta[k], (bh - bprev) * K.inv_ds, res[k][MB]);
+            }
+#pragma unroll
+            for (int m = 0; m < 3; ++m) fprev[m] = Fh[m];
+            bprev = bh;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// wave64 reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned int wave_max_u32(unsigned int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned int u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Float bits of a non-negative speed; any non-finite value maps to +inf so
+// that the unsigned max keeps it.
+__device__ __forceinline__ unsigned int speed_bits(float s)
+{
+    return (s <= 3.4e38f) ? __float_as_uint(s) : 0x7f800000u;
+}
+
+// ---------------------------------------------------------------------------
+// The stage on one tile
+// ---------------------------------------------------------------------------
+// STAGE 1: w = u^n -> A;  2: w = A -> B;  3: w = B -> u^n (in place: each
+// cell of u^n is read and then written by the same thread, and no halo of
+// stage 3 reads u^n).
+template <class C>
+__device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *lds, const int STAGE)
+{
+    constexpr int TX = C::TX, TY = C::TY, R = C::R, NT = C::NT;
+    float *Lh = lds, *Lhu = lds + C::PLANE, *Lhv = lds + 2 * C::PLANE, *Lb = lds + 3 * C::PLANE;
+    float *Xr = lds + 4 * C::PLANE;
+    const int tid = threadIdx.x;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int nx = G.nx, ny = G.ny, pitch = G.pitch;
+    DevScen *sd = G.sd;
+
+    const float *const *W = STAGE == 1 ? G.U : STAGE == 2 ? G.A : G.B;
+    float *const *O = STAGE == 1 ? G.A : STAGE == 2 ? G.B : G.U;
+    const float *w0 = W[0], *w1 = W[1], *w2 = W[2];
+
+    // ---- stage scalars ------------------------------------------------------
+    const float ax = __uint_as_float(__hip_atomic_load(&sd->alpha[STAGE - 1][0], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT));
+    const float ay = __uint_as_float(__hip_atomic_load(&sd->alpha[STAGE - 1][1], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT));
+    float dt;
+    if (STAGE == 1) {
+        if (G.cfl > 0.f) {
+            const double den = (double)ax * (double)G.inv_dx + (double)ay * (double)G.inv_dy;
+            dt = (den > 0.0 && den < 1e300) ? (float)((double)G.cfl / den) : 0.f;
+        } else {
+            dt = G.dt_fixed;
+        }
+    } else {
+        dt = __hip_atomic_load(&sd->dt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const float kcap = (G.kappa_cap > 0.f && dt > 0.f) ? G.kappa_cap / dt : 3.0e38f;
+
+    // ---- 1. stage the input tile and its cross-shaped halo in LDS ----------
+    for (int e = tid; e < C::WX * C::WY; e += NT) {
+        const int r = e / C::WX;
+        const int cc = e - r * C::WX;
+        const bool hx = cc < HALO || cc >= TX + HALO;
+        const bool hy = r < HALO || r >= TY + HALO;
+        if (hx && hy) continue;  // tile corners are never read
+        const int gx = x0 - HALO + cc, gy = y0 - HALO + r;
+        const bool inx = (unsigned)gx < (unsigned)nx, iny = (unsigned)gy < (unsigned)ny;
+        float h = 0.f, hu = 0.f, hv = 0.f, b = 0.f;
+        if (inx && iny) {
+            const int i = gy * pitch + gx;
+            h = w0[i];
+            hu = w1[i];
+            hv = w2[i];
+            b = G.b[i];
+        } else if (inx != iny) {
+            int side = -1, layer = 0, pos = 0, sx = gx, sy = gy;
+            if (!inx) {
+                if (gx < 0 && gx >= -HALO) { side = 0; layer = -1 - gx; sx = layer; }
+                else if (gx >= nx && gx < nx + HALO) { side = 1; layer = gx - nx; sx = nx - 1 - layer; }
+                pos = gy;
+            } else {
+                if (gy < 0 && gy >= -HALO) { side = 2; layer = -1 - gy; sy = layer; }
+                else if (gy >= ny && gy < ny + HALO) { side = 3; layer = gy - ny; sy = ny - 1 - layer; }
+                pos = gx;
+            }
+            if (side >= 0) {
+                if (G.bc[side] == BC_REFLECT) {
+                    const int i = sy * pitch + sx;
+                    h = w0[i];
+                    hu = w1[i];
+                    hv = w2[i];
+                    b = G.b[i];
+                    if (side < 2) hu = -hu; else hv = -hv;
+                } else {
+                    h = G.ghost[ghost_index(G, side, 0, layer, pos)];
+                    hu = G.ghost[ghost_index(G, side, 1, layer, pos)];
+                    hv = G.ghost[ghost_index(G, side, 2, layer, pos)];
+                    b = G.ghost[ghost_index(G, side, 3, layer, pos)];
+                }
+            }
+        }
+        const int li = r * C::SX + cc;
+        Lh[li] = h;
+        Lhu[li] = hu;
+        Lhv[li] = hv;
+        Lb[li] = b;
+    }
+    __syncthreads();
+
+    SweepK K;
+    K.g = G.g;
+    K.half_g = G.half_g;
+    K.h_dry = G.h_dry;
+    K.e0 = G.eps12 * KD0;
+    K.e1 = G.eps12 * KD1;
+    K.e2 = G.eps12 * KD2;
+
+    // ---- 2. x sweep: thread -> (row, segment of R cells) -------------------
+    {
+        const int row = tid % TY, seg = tid / TY;
+        K.ha = 0.5f * ax;
+        K.inv_ds = G.inv_dx;
+        float res[R][3];
+        sweep<R, 0>(Lh, Lhu, Lhv, Lb, (row + HALO) * C::SX + seg * R, 1, K, res);
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) Xr[m * C::XPLANE + row * C::XR + seg * R + k] = res[k][m];
+    }
+    __syncthreads();
+
+    // ---- 3. y sweep, sources, RK combination, store, reductions -------------
+    const int col = tid % TX, seg = tid / TX;
+    const int gx = x0 + col;
+    float res[R][3];
+    K.ha = 0.5f * ay;
+    K.inv_ds = G.inv_dy;
+    sweep<R, 1>(Lh, Lhu, Lhv, Lb, (seg * R) * C::SX + col + HALO, C::SX, K, res);
+
+    unsigned int sxb = 0, syb = 0, rub = 0;
+    float deficit = 0.f;
+    const float h_dry = G.h_dry;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int ly = seg * R + k;
+        const int gy = y0 + ly;
+        if (gx >= nx || gy >= ny) continue;
+        const int gi = gy * pitch + gx;
+        const int li = (ly + HALO) * C::SX + col + HALO;
+        const int xi = ly * C::XR + col;
+        const float h = Lh[li], hu = Lhu[li], hv = Lhv[li];
+        float Lh_ = Xr[xi] + res[k][0];
+        float Lhu_ = Xr[C::XPLANE + xi] + res[k][1];
+        float Lhv_ = Xr[2 * C::XPLANE + xi] + res[k][2];
+        // explicit Manning friction, wet cells only, rate capped at kappa_cap/dt
+        const float gn2 = G.gn2[gi];
+        if (h > h_dry && gn2 > 0.f) {
+            const float qn = sqrtf(fmaf(hu, hu, hv * hv));
+            const float hm73 = __builtin_amdgcn_exp2f(-2.33333333333333f * __builtin_amdgcn_logf(h));
+            const float kap = fminf(gn2 * qn * hm73, kcap);
+            Lhu_ = fmaf(-kap, hu, Lhu_);
+            Lhv_ = fmaf(-kap, hv, Lhv_);
+        }
+        float oh = fmaf(dt, Lh_, h), ohu = fmaf(dt, Lhu_, hu), ohv = fmaf(dt, Lhv_, hv);
+        if (STAGE == 2) {
+            oh = fmaf(0.75f, G.U[0][gi], 0.25f * oh);
+            ohu = fmaf(0.75f, G.U[1][gi], 0.25f * ohu);
+            ohv = fmaf(0.75f, G.U[2][gi], 0.25f * ohv);
+        }
+        if (STAGE == 3) {
+            // u^n + (2/3)(w + dt L - u^n): the FP32 weights 1/3 and 2/3 sum
+            // to 1 + 3e-8, which would create mass every step; this form
+            // keeps the two weights summing to exactly one
+            const float un0 = G.U[0][gi], un1 = G.U[1][gi], un2 = G.U[2][gi];
+            oh = fmaf(2.f / 3.f, oh - un0, un0);
+            ohu = fmaf(2.f / 3.f, ohu - un1, un1);
+            ohv = fmaf(2.f / 3.f, ohv - un2, un2);
+        }
+        if (oh < 0.f) {
+            deficit -= oh;
+            oh = 0.f;
+        }
+        const bool wet = oh > h_dry;
+        if (!wet) {
+            ohu = 0.f;
+            ohv = 0.f;
+        }
+        O[0][gi] = oh;
+        O[1][gi] = ohu;
+        O[2][gi] = ohv;
+        // wave speeds of the output (the next stage's input)
+        const float cel = sqrtf(G.g * oh);
+        const float inv = wet ? frcp(oh) : 0.f;
+        const bool fin = fabsf(oh) <= 3.4e38f && fabsf(ohu) <= 3.4e38f && fabsf(ohv) <= 3.4e38f;
+        const unsigned int bx = fin ? speed_bits(fabsf(ohu * inv) + cel) : 0x7f800000u;
+        const unsigned int by = fin ? speed_bits(fabsf(ohv * inv) + cel) : 0x7f800000u;
+        sxb = bx > sxb ? bx : sxb;
+        syb = by > syb ? by : syb;
+        if (STAGE == 3) {
+            const float bb = Lb[li];
+            if (wet && bb > 0.f) {
+                const unsigned int u = __float_as_uint(bb);
+                rub = u > rub ? u : rub;
+            }
+        }
+    }
+
+    // ---- epilogue: block reductions ------------------------------------------
+    sxb = wave_max_u32(sxb);
+    syb = wave_max_u32(syb);
+    const bool any_def = __any(deficit > 0.f);
+    double dsum = any_def ? wave_sum_f64((double)deficit) : 0.0;
+    if (STAGE == 3) rub = wave_max_u32(rub);
+    __syncthreads();  // LDS tile no longer needed
+    constexpr int NW = NT / 64;
+    unsigned int *ru = reinterpret_cast<unsigned int *>(lds);
+    double *rd = reinterpret_cast<double *>(lds + 4 * NW);
+    const int lane = tid & 63, wv = tid >> 6;
+    if (lane == 0) {
+        ru[wv] = sxb;
+        ru[NW + wv] = syb;
+        ru[2 * NW + wv] = rub;
+        rd[wv] = dsum;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        unsigned int mx = 0, my = 0, mr = 0;
+        double ds = 0.0;
+        for (int i = 0; i < NW; ++i) {
+            mx = ru[i] > mx ? ru[i] : mx;
+            my = ru[NW + i] > my ? ru[NW + i] : my;
+            mr = ru[2 * NW + i] > mr ? ru[2 * NW + i] : mr;
+            ds += rd[i];
+        }
+        // Same-address atomics from every block serialise; the running maxima
+        // only grow, so a block whose partial does not exceed the value
+        // already there skips its atomic (the load may lag, never lead).
+        const int out_slot = STAGE % 3;  // stage 1 -> slot 1, 2 -> 2, 3 -> 0
+        unsigned int *ax_slot = &sd->alpha[out_slot][0], *ay_slot = &sd->alpha[out_slot][1];
+        if (mx > __hip_atomic_load(ax_slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(ax_slot, mx);
+        if (my > __hip_atomic_load(ay_slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(ay_slot, my);
+        const double wgt = STAGE == 1 ? 1.0 / 6.0 : STAGE == 2 ? 2.0 / 3.0 : 1.0;
+        if (ds != 0.0) atomicAdd(&sd->clamp_sum, wgt * ds);
+        if (STAGE == 3 && mr > __hip_atomic_load(&sd->runup, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&sd->runup, mr);
+        if ((mx >= 0x7f800000u || my >= 0x7f800000u)) atomicOr(&sd->flags, 1u);
+        // bookkeeping done once per stage by the first tile
+        if (tx == 0 && ty == 0) {
+            if (STAGE == 1) {
+                sd->dt = dt;
+                sd->alpha[2][0] = 0u;
+                sd->alpha[2][1] = 0u;
+            } else if (STAGE == 2) {
+                sd->alpha[0][0] = 0u;
+                sd->alpha[0][1] = 0u;
+            } else {
+                sd->alpha[1][0] = 0u;
+                sd->alpha[1][1] = 0u;
+                sd->t += (double)dt;
+                sd->step += 1;
+            }
+        }
+    }
+}
+
+}  // namespace swe

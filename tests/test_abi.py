@@ -1,0 +1,74 @@
+"""The C ABI: every function declared in include/swe.h is exported by
+libswe.so and declared by the Python binding; host-only calls work without a
+GPU.  The FP64 checker's library exports its entry points too."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2301_12010_amd import swe
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "swe.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(swe_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary_calls():
+    names = header_functions()
+    for required in ("swe_create", "swe_step", "swe_read", "swe_destroy", "swe_submit", "swe_poll",
+                     "swe_batch_create", "swe_batch_add", "swe_batch_run", "swe_server_create",
+                     "swe_autotune"):
+        assert required in names
+
+
+def test_library_exports_every_header_function():
+    if not swe.LIB_PATH.exists():
+        pytest.fail("libswe.so is not built")
+    L = ctypes.CDLL(str(swe.LIB_PATH))
+    missing = [n for n in header_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_declares_every_header_function():
+    missing = set(header_functions()) - set(swe.exported_names())
+    assert not missing, missing
+
+
+def test_host_only_calls():
+    L = swe.lib()
+    assert L.swe_strerror(swe.ENONFINITE).decode().startswith("non-finite")
+    assert L.swe_strerror(12345) == b"unknown error"
+    # 11 planes of 4096 floats x 4096 rows plus ghosts and scalars
+    fp = swe.footprint(4096, 4096)
+    assert 11 * 4096 * 4096 * 4 <= fp < 11 * 4096 * 4096 * 4 + 2 ** 20
+    assert swe.footprint(0, 5) == 0
+    assert L.swe_tile_count() >= 4
+    v = swe.tile_variants()
+    assert all(t["tx"] * t["ty"] // t["r"] == t["threads"] and t["threads"] % 64 == 0 for t in v)
+    # null handles are rejected without touching the GPU
+    assert L.swe_step(None, 1) == swe.EINVAL
+    assert L.swe_read(None, None, None, None, None) == swe.EINVAL
+    L.swe_destroy(None)
+    L.swe_batch_destroy(None)
+    L.swe_server_destroy(None)
+
+
+def test_params_struct_layout_matches_header():
+    # int32 nx, ny; 8 doubles; int32 bc[4]  -> 4 + 4 + 64 + 16 = 88 bytes
+    assert ctypes.sizeof(swe.Params) == 88
+    # t, step, mass, clamp_mass, dt (8 bytes each); alpha_x, alpha_y, runup, status
+    assert ctypes.sizeof(swe.Stats) == 8 * 5 + 4 * 4
+
+
+def test_checker_library_exports():
+    import oracle
+    L = oracle.lib()
+    for n in ("oracle_create", "oracle_step", "oracle_read", "oracle_scalars", "oracle_rhs",
+              "oracle_weno5", "oracle_destroy"):
+        assert hasattr(L, n)
