@@ -1,16 +1,22 @@
-"""Benchmark: cell-RK3-updates/s of the FP32 shallow-water step on one MI355X.
+"""Benchmark of the FP32 shallow-water step on one MI355X.
 
-Default workload: the single large synthetic coastline (4096 x 4096 cells,
-dx = 5 m, linear beach + 32 seeded bumps + a 2 m plane hump, Manning
-n = 0.025, h_dry = 1e-3, CFL 0.4), inputs resident in HBM before timing.
-One bench "step" is one full TVD-RK3 step (three stage kernels: halo
-staging, WENO5/LF faces in x and y, sources, RK combination, wave-speed,
-mass and runup reductions, device-side dt) over the whole grid.
+Main line (``value``): cell-RK3-updates/s on the single large synthetic
+coastline: 4096 x 4096 cells, dx = 5 m, linear beach + 32 seeded bumps + a
+2 m plane hump, Manning n = 0.025, h_dry = 1e-3, CFL 0.4.  Inputs are
+resident in HBM before timing.  One bench "step" is one full TVD-RK3 step
+(three stage kernels: halo staging, WENO5/LF faces in x and y, sources, RK
+combination, wave-speed and runup reductions, device-side dt) over the grid.
 
-Prints one JSON line.  ``roofline`` covers the stage kernel: algorithmic
-bytes and flops per launch over its mean device duration, timed with HIP
-events on the stream the kernels run on.  ``cpu_baseline`` times the FP64
-reference checker on a bounded sample of the same workload.
+Extra objects on the same JSON line:
+  roofline      stage kernel: algorithmic flops (and bytes) per launch over
+                its mean device duration, HIP events on the kernels' stream;
+  cpu_baseline  the FP64 reference checker on a bounded sample;
+  batched       the mitigation ensemble (64 x 1024^2, dx 2 m, 3000 steps,
+                seeded hills and Manning patches) in one batch: scenarios/hour
+                batched vs the plain single-scenario solver, runup;
+  serving       Poisson arrivals of ensemble-sized requests at 0.7x the
+                measured batched capacity: p50/p99 time-to-result,
+                scenarios/hour, device-memory high-water mark.
 """
 import argparse
 import hashlib
@@ -37,6 +43,10 @@ FLOPS_STAGE = 2 * 25 + 2 * (6 * 70 + 3 + 48 + 10) + 16 + 15 + 7
 HBM_PEAK = 8.0e12        # B/s
 FP32_PEAK_UNPACKED = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FP32_PEAK_PUBLISHED = 157.3e12  # with packed (dual) FP32, not used by this build
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def kernel_source_digest():
@@ -68,7 +78,7 @@ def cpu_baseline(sc, budget_s=15.0):
         o.step(1)
         steps += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 50 or (steps >= 1 and el * (steps + 1) / steps > 2 * budget_s):
+        if el >= budget_s or steps >= 50 or el * (steps + 1) / steps > 2 * budget_s:
             break
     rate = sc.cells * steps / el
     return {"value": rate, "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
@@ -76,58 +86,33 @@ def cpu_baseline(sc, budget_s=15.0):
                       f"RK3 step(s) from the same initial state ({el:.1f} s)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--nx", type=int, default=4096)
-    ap.add_argument("--ny", type=int, default=4096)
-    ap.add_argument("--tile", type=int, default=-1)
-    ap.add_argument("--graph-steps", type=int, default=50)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
-    args = ap.parse_args()
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    from paper_2301_12010_amd import inputs, swe
-
-    torch.cuda.set_device(0)
+def run_large(args, torch, inputs, swe):
     t_gen = time.perf_counter()
     sc = inputs.large_coast(args.nx, args.ny, 5.0 * 4096 / args.nx, seed=2, nsteps=2000)
-    t_gen = time.perf_counter() - t_gen
-    print(f"[bench] generated {sc.name} in {t_gen:.1f}s", file=sys.stderr, flush=True)
-
+    log(f"generated {sc.name} in {time.perf_counter() - t_gen:.1f}s")
+    tile = args.tile
+    if tile < 0:
+        tile, _ = swe.autotune(sc.params.nx, sc.params.ny)
+        log(f"autotuned tile variant {tile}")
     stream = torch.cuda.Stream()  # default priority; the solver's kernels run here
     s = swe.Solver.from_scenario(sc, stream=stream)
-    if args.tile >= 0:
-        s.set_option(swe.OPT_TILE, args.tile)
+    s.set_option(swe.OPT_TILE, tile)
     s.set_option(swe.OPT_GRAPH_STEPS, args.graph_steps)
     s.step(args.warmup)
     torch.cuda.synchronize()
-    print("[bench] warmup done", file=sys.stderr, flush=True)
-
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     start.record(stream)
     s.step(args.steps)
     stop.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     ms = start.elapsed_time(stop)
     st = s.stats()
     if st["rc"] != 0:
         raise RuntimeError(f"solver state non-finite after timing: {st}")
     value = sc.cells * args.steps / (ms * 1e-3)
-    print(f"[bench] timed {args.steps} steps: {ms:.1f} ms (wall {wall:.2f}s), t={st['t']:.2f}s",
-          file=sys.stderr, flush=True)
+    log(f"timed {args.steps} steps: {ms:.1f} ms, t={st['t']:.2f}s, {value:.3e} {UNIT}")
 
     # stage-kernel durations with HIP events around each launch (plain launches)
     kms = s.time_stages(20)
@@ -148,23 +133,162 @@ def main():
                 "bytes_per_cell_launch": sum(BYTES_STAGE) / 3.0}
     roofline = roof_alu if roof_alu["frac"] >= roof_hbm["frac"] else roof_hbm
     other = roof_hbm if roofline is roof_alu else roof_alu
+    tv = swe.tile_variants()[tile]
+    s.close()
+    return sc, value, ms, roofline, other, tv
 
-    tile = swe.tile_variants()[args.tile if args.tile >= 0 else 0]
+
+def run_batched(args, torch, inputs, swe):
+    """Mitigation ensemble: scenarios/hour batched vs the plain solver."""
+    t0 = time.perf_counter()
+    members = inputs.mitigation_ensemble(args.ens_count, 1024, 1024, args.ens_steps)
+    log(f"generated {len(members)} ensemble members in {time.perf_counter() - t0:.1f}s")
+    cells = 1024 * 1024
+    out = {"workload": f"mitigation_ensemble_{len(members)}x1024x1024_dx2", "scenarios": len(members),
+           "steps_per_scenario": args.ens_steps}
+    modes = [("rounds_graph", swe.BATCH_ROUNDS, True), ("persistent", swe.BATCH_PERSISTENT, False)]
+    for name, mode, graph in modes:
+        bt = swe.Batch()
+        bt.set_mode(mode, graph)
+        for sc in members:
+            bt.add_scenario(sc)
+        steps = args.ens_steps if name == "rounds_graph" else min(args.ens_steps, 300)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        bt.run(steps)
+        st0 = bt.stats(0)
+        dt = time.perf_counter() - t
+        rate = len(members) * cells * steps / dt
+        out[name] = {"steps": steps, "seconds": dt, "cell_updates_per_s": rate}
+        if name == "rounds_graph":
+            runups = [bt.stats(i)["runup"] for i in range(len(members))]
+            assert all(bt.stats(i)["rc"] == 0 for i in range(len(members)))
+            out["scenarios_per_hour"] = len(members) / dt * 3600.0
+            out["runup_m"] = {"min": min(runups), "median": sorted(runups)[len(runups) // 2],
+                              "max": max(runups)}
+        log(f"batched {name}: {steps} steps in {dt:.2f}s, {rate:.3e} cell-updates/s")
+        bt.close()
+    # plain single-scenario solver, one scenario at a time (same inputs, same steps)
+    k = min(2, len(members))
+    t = time.perf_counter()
+    for sc in members[:k]:
+        s = swe.Solver.from_scenario(sc)
+        s.step(args.ens_steps)
+        s.stats()
+        s.close()
+    dt = (time.perf_counter() - t) / k
+    out["plain_solver_scenarios_per_hour"] = 3600.0 / dt
+    out["plain_solver_cell_updates_per_s"] = cells * args.ens_steps / dt
+    out["batched_over_plain"] = out["scenarios_per_hour"] / out["plain_solver_scenarios_per_hour"]
+    log(f"plain solver {dt:.2f}s per scenario")
+    return out, members
+
+
+def run_serving(args, swe, members, capacity_per_s):
+    """Poisson arrivals at 0.7x the batched capacity; time-to-result percentiles."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(5))
+    n = args.serve_requests
+    steps = rng.integers(args.serve_steps // 2, args.serve_steps * 3 // 2 + 1, size=n)
+    mean_steps = float(np.mean(steps))
+    rate = 0.7 * capacity_per_s * args.ens_steps / mean_steps  # requests per second
+    gaps = rng.exponential(1.0 / rate, size=n)
+    sv = swe.Server(mem_budget=args.serve_budget_gb << 30, max_slots=64, segment_steps=100)
+    sv.set_mode(swe.BATCH_ROUNDS)
+    t_start = time.perf_counter()
+    t_next = t_start
+    pending, results = {}, []
+    for i in range(n):
+        t_next += gaps[i]
+        while time.perf_counter() < t_next:
+            for tk in list(pending):
+                r, _ = sv.poll(tk, want_state=False)
+                if r["status"] != swe.PENDING:
+                    results.append(r)
+                    del pending[tk]
+            time.sleep(0.001)
+        sc = members[i % len(members)]
+        pending[sv.submit_scenario(sc, int(steps[i]))] = i
+    while pending:
+        for tk in list(pending):
+            r, _ = sv.poll(tk, want_state=False)
+            if r["status"] != swe.PENDING:
+                results.append(r)
+                del pending[tk]
+        time.sleep(0.002)
+    st = sv.stats()
+    sv.close()
+    ok = [r for r in results if r["status"] == swe.DONE]
+    ttr = np.array([r["t_done"] - r["t_submit"] for r in ok])
+    span = max(r["t_done"] for r in ok) - min(r["t_submit"] for r in ok)
+    return {"workload": "poisson_requests_1024x1024_dx2", "requests": n, "completed": len(ok),
+            "arrival_rate_per_s": rate, "steps_per_request": [int(steps.min()), int(steps.max())],
+            "p50_time_to_result_s": float(np.percentile(ttr, 50)),
+            "p99_time_to_result_s": float(np.percentile(ttr, 99)),
+            "scenarios_per_hour": len(ok) / span * 3600.0,
+            "mem_budget_bytes": st["mem_budget"], "mem_high_water_bytes": st["mem_high_water"],
+            "segments": st["segments"]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--nx", type=int, default=4096)
+    ap.add_argument("--ny", type=int, default=4096)
+    ap.add_argument("--tile", type=int, default=-1)
+    ap.add_argument("--graph-steps", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-batched", action="store_true", help="skip the ensemble and serving runs")
+    ap.add_argument("--ens-count", type=int, default=64)
+    ap.add_argument("--ens-steps", type=int, default=3000)
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-steps", type=int, default=1000)
+    ap.add_argument("--serve-budget-gb", type=int, default=2)
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2301_12010_amd import inputs, swe
+
+    torch.cuda.set_device(0)
+    sc, value, ms, roofline, other, tv = run_large(args, torch, inputs, swe)
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": sc.name, "nx": sc.params.nx, "ny": sc.params.ny,
-                   "dx": sc.params.dx, "cells": n, "cfl": sc.params.cfl,
-                   "tile": [tile["tx"], tile["ty"], tile["r"]],
-                   "graph_steps": args.graph_steps},
+                   "dx": sc.params.dx, "cells": sc.cells, "cfl": sc.params.cfl,
+                   "tile": [tv["tx"], tv["ty"], tv["r"]], "graph_steps": args.graph_steps},
         "roofline": roofline, "roofline_other": other,
     }
-    s.close()
-    del s
+    if not args.no_batched:
+        batched, members = run_batched(args, torch, inputs, swe)
+        out["batched"] = batched
+        cap = batched["scenarios_per_hour"] / 3600.0
+        log(f"serving {args.serve_requests} requests ...")
+        out["serving"] = run_serving(args, swe, members, cap)
+        del members
+    if args.calibrate_copy_mb > 0:
+        n = args.calibrate_copy_mb * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 4 * n
+        del a, b
     if not args.no_cpu:
-        print("[bench] cpu baseline ...", file=sys.stderr, flush=True)
+        log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)
     print(json.dumps(out), flush=True)
 

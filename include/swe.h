@@ -135,7 +135,7 @@ int swe_tile_count(void);
 int swe_autotune(int32_t nx, int32_t ny, const char *cache_path, int32_t *best_tile,
                  double *best_ms_per_step);
 
-/* ---- batched scenarios (one persistent launch for all) ------------------ */
+/* ---- batched scenarios (one launch sequence for all) -------------------- */
 typedef struct swe_batch swe_batch;
 
 /* Empty batch bound to hip_stream (NULL: own stream). */
@@ -154,7 +154,8 @@ int swe_batch_run(swe_batch *bt, int32_t max_steps);
 /* Wait, then copy scenario `index` (pointers may be NULL). */
 int swe_batch_read(swe_batch *bt, int32_t index, float *h, float *hu, float *hv, swe_stats *stats);
 
-/* Launch modes of swe_batch_run (swe_batch_set_mode). */
+/* Launch modes of swe_batch_run (swe_batch_set_mode).  Default: ROUNDS
+ * captured as one hipGraph per run (the faster mode on MI355X). */
 #define SWE_BATCH_PERSISTENT 0 /* one persistent kernel, tile tickets, per-scenario barriers */
 #define SWE_BATCH_ROUNDS 1     /* one launch per stage covering every active scenario */
 int swe_batch_set_mode(swe_batch *bt, int32_t mode, int32_t use_graph);
@@ -207,6 +208,10 @@ int swe_submit(swe_server *sv, const swe_params *p, const float *b, const float 
  * status (DONE, FAILED, CANCELLED) has been returned once; afterwards it is
  * SWE_ENOTFOUND. */
 int swe_poll(swe_server *sv, uint64_t ticket, swe_result *r, float *h, float *hu, float *hv);
+
+/* Launch mode of the server's segments (SWE_BATCH_ROUNDS, the default, or
+ * SWE_BATCH_PERSISTENT); takes effect at the next segment. */
+int swe_server_set_mode(swe_server *sv, int32_t mode);
 
 /* Cancel a queued or running request (it ends as SWE_CANCELLED). */
 int swe_cancel(swe_server *sv, uint64_t ticket);

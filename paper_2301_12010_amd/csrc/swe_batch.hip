@@ -79,27 +79,38 @@ __global__ __launch_bounds__(C::NT, 2) void k_persistent(BatchTables T)
         __syncthreads();
         if (t0 >= total) break;
         const long long t1 = t0 + T.group < total ? t0 + T.group : total;
+        // locate the first ticket of the group; later ones step forward
+        int r = upper_index(T.rstart, T.nrounds, t0);
+        int l = (int)(t0 - T.rstart[r]);
+        int nr = T.ractive[r];
+        int slot = upper_index(T.prefix, nr, l);
         for (long long t = t0; t < t1; ++t) {
-            const int r = upper_index(T.rstart, T.nrounds, t);
-            const int l = (int)(t - T.rstart[r]);
-            const int slot = upper_index(T.prefix, T.ractive[r], l);
+            if (t >= T.rstart[r + 1]) {  // next round
+                ++r;
+                l = 0;
+                slot = 0;
+                nr = T.ractive[r];
+            }
+            while (l >= T.prefix[slot + 1]) ++slot;
             const int tl = l - T.prefix[slot];
             const int ntx = T.ntx[slot];
             const int ntiles = T.prefix[slot + 1] - T.prefix[slot];
             const Geo &G = T.geo[T.order[slot]];
-            // every tile of this scenario's previous round must be complete
+            // every tile of this scenario's previous round must be complete;
+            // one wave waits and acquires, the barrier orders the others
             if (threadIdx.x == 0) {
                 const unsigned int need = (unsigned int)ntiles * (unsigned int)r;
                 while (__hip_atomic_load(&T.done[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need)
                     __builtin_amdgcn_s_sleep(1);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             stage_tile<C>(G, tl % ntx, tl / ntx, lds, r % 3 + 1);
             __syncthreads();
-            if (threadIdx.x == 0) {
+            if (threadIdx.x == 0)
                 __hip_atomic_fetch_add(&T.done[slot], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            }
+            ++l;
+            (void)nr;
         }
     }
 }
@@ -287,8 +298,8 @@ struct swe_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::vector<BatchScen> sc;
-    int mode = SWE_BATCH_PERSISTENT;
-    bool use_graph = false;
+    int mode = SWE_BATCH_ROUNDS;
+    bool use_graph = true;
     int tile = -1;
     SegmentLauncher seg;
 };

@@ -120,6 +120,7 @@ struct swe_server {
     int device = 0;
     int max_slots = 64;
     int segment_steps = 100;
+    int mode = SWE_BATCH_ROUNDS;
     size_t max_queue = 1 << 16;
     Arena arena;
     hipStream_t compute = nullptr, copy = nullptr;
@@ -217,8 +218,12 @@ void swe_server::loop()
             int big = 0;
             for (size_t i = 1; i < geos.size(); ++i)
                 if ((size_t)geos[i].nx * geos[i].ny > (size_t)geos[big].nx * geos[big].ny) big = (int)i;
-            rc = seg.run(geos, ks, default_variant(geos[big].nx, geos[big].ny), SWE_BATCH_PERSISTENT, false,
-                         compute);
+            int launch_mode;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                launch_mode = mode;
+            }
+            rc = seg.run(geos, ks, default_variant(geos[big].nx, geos[big].ny), launch_mode, false, compute);
             std::lock_guard<std::mutex> lk(mu);
             ++segments;
             if (rc) fatal = rc;
@@ -362,6 +367,14 @@ int swe_poll(swe_server *sv, uint64_t ticket, swe_result *res, float *h, float *
         if (hv) std::memcpy(hv, r->hv.data(), N * sizeof(float));
     }
     sv->reqs.erase(it);  // a final status is reported once
+    return SWE_OK;
+}
+
+int swe_server_set_mode(swe_server *sv, int32_t mode)
+{
+    if (!sv || (mode != SWE_BATCH_PERSISTENT && mode != SWE_BATCH_ROUNDS)) return SWE_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->mode = mode;
     return SWE_OK;
 }
 

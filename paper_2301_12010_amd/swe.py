@@ -102,6 +102,7 @@ _SIGS = {
                                   ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
     "swe_poll": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(Result), _FP, _FP, _FP]),
     "swe_cancel": (ctypes.c_int, [_VP, ctypes.c_uint64]),
+    "swe_server_set_mode": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "swe_server_get_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ServerStats)]),
     "swe_server_destroy": (None, [_VP]),
     "swe_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -371,6 +372,9 @@ class Server:
             self._shapes.pop(ticket, None)
         state = tuple(arrs) if (want_state and d["status"] == DONE) else None
         return d, state
+
+    def set_mode(self, mode: int):
+        _check(_lib().swe_server_set_mode(self._sv, int(mode)), "swe_server_set_mode")
 
     def cancel(self, ticket: int):
         _check(_lib().swe_cancel(self._sv, int(ticket)), "swe_cancel")
