@@ -147,8 +147,9 @@ int swe_batch_add(swe_batch *bt, const swe_params *p, const float *b, const floa
                   const float *h0, const float *hu0, const float *hv0, int32_t nsteps,
                   int32_t *index);
 
-/* Advance every scenario by min(max_steps, its remaining steps) in one
- * persistent launch (max_steps < 0: to completion).  Asynchronous. */
+/* Advance every scenario by min(max_steps, its remaining steps) in one run:
+ * one persistent launch, or one launch per stage round (see
+ * swe_batch_set_mode); max_steps < 0 runs to completion.  Asynchronous. */
 int swe_batch_run(swe_batch *bt, int32_t max_steps);
 
 /* Wait, then copy scenario `index` (pointers may be NULL). */

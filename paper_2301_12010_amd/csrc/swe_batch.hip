@@ -66,8 +66,8 @@ struct BatchTables {
     int nrounds, nact, group;
 };
 
-template <class C>
-__global__ __launch_bounds__(C::NT, 2) void k_persistent(BatchTables T)
+template <class C, int W>
+__global__ __launch_bounds__(C::NT, W) void k_persistent(BatchTables T)
 {
     __shared__ float lds[C::LDS_FLOATS];
     __shared__ long long s_ticket;
@@ -115,8 +115,8 @@ __global__ __launch_bounds__(C::NT, 2) void k_persistent(BatchTables T)
     }
 }
 
-template <class C, int S>
-__global__ __launch_bounds__(C::NT, 2) void k_round(BatchTables T, int nact_round, int nblocks)
+template <class C, int S, int W>
+__global__ __launch_bounds__(C::NT, W) void k_round(BatchTables T, int nact_round, int nblocks)
 {
     __shared__ float lds[C::LDS_FLOATS];
     const int id = xcd_remap_b(blockIdx.x, nblocks);
@@ -138,13 +138,15 @@ struct BatchKernels {
     void (*round[3])(BatchTables, int, int);
 };
 
-#define SWE_BK(TX, TY, R)                                                                          \
-    {k_persistent<TileCfg<TX, TY, R>>,                                                             \
-     {k_round<TileCfg<TX, TY, R>, 1>, k_round<TileCfg<TX, TY, R>, 2>, k_round<TileCfg<TX, TY, R>, 3>}},
+#define SWE_BK(TX, TY, R, W)                                                                  \
+    {k_persistent<TileCfg<TX, TY, R>, W>,                                                     \
+     {k_round<TileCfg<TX, TY, R>, 1, W>, k_round<TileCfg<TX, TY, R>, 2, W>,                    \
+      k_round<TileCfg<TX, TY, R>, 3, W>}},
 
 // same order as the single-scenario variant table
-static const BatchKernels g_bk[] = {SWE_BK(64, 16, 8) SWE_BK(64, 32, 8) SWE_BK(32, 32, 8)
-                                        SWE_BK(64, 16, 4) SWE_BK(128, 16, 8)};
+static const BatchKernels g_bk[] = {SWE_BK(64, 16, 8, 2) SWE_BK(64, 32, 8, 2) SWE_BK(32, 32, 8, 2)
+                                        SWE_BK(64, 16, 4, 2) SWE_BK(128, 16, 8, 2) SWE_BK(64, 16, 4, 3)
+                                            SWE_BK(32, 32, 4, 3) SWE_BK(32, 32, 4, 4)};
 
 // ---------------------------------------------------------------------------
 // segment launcher (shared by swe_batch and the server)

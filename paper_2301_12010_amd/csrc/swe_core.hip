@@ -24,8 +24,8 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return x * q + (x < r ? x : r) + l;
 }
 
-template <class C, int S>
-__global__ __launch_bounds__(C::NT, 2) void k_stage(Geo G, int ntx, int nblocks)
+template <class C, int S, int W>
+__global__ __launch_bounds__(C::NT, W) void k_stage(Geo G, int ntx, int nblocks)
 {
     __shared__ float lds[C::LDS_FLOATS];
     const int id = xcd_remap(blockIdx.x, nblocks);
@@ -121,16 +121,20 @@ int launch_mass(const Geo &g, hipStream_t stream)
 // ---------------------------------------------------------------------------
 // tile variants
 // ---------------------------------------------------------------------------
+// (tile width, tile height, cells per thread per sweep, minimum waves per SIMD)
 #define SWE_TILE_LIST(X) \
-    X(64, 16, 8)         \
-    X(64, 32, 8)         \
-    X(32, 32, 8)         \
-    X(64, 16, 4)         \
-    X(128, 16, 8)
+    X(64, 16, 8, 2)      \
+    X(64, 32, 8, 2)      \
+    X(32, 32, 8, 2)      \
+    X(64, 16, 4, 2)      \
+    X(128, 16, 8, 2)     \
+    X(64, 16, 4, 3)      \
+    X(32, 32, 4, 3)      \
+    X(32, 32, 4, 4)
 
-#define SWE_VARIANT(TX, TY, R)                                                          \
-    {TX, TY, R, TileCfg<TX, TY, R>::NT, sizeof(float) * TileCfg<TX, TY, R>::LDS_FLOATS, \
-     {k_stage<TileCfg<TX, TY, R>, 1>, k_stage<TileCfg<TX, TY, R>, 2>, k_stage<TileCfg<TX, TY, R>, 3>}},
+#define SWE_VARIANT(TX, TY, R, W)                                                         \
+    {TX, TY, R, TileCfg<TX, TY, R>::NT, W, sizeof(float) * TileCfg<TX, TY, R>::LDS_FLOATS, \
+     {k_stage<TileCfg<TX, TY, R>, 1, W>, k_stage<TileCfg<TX, TY, R>, 2, W>, k_stage<TileCfg<TX, TY, R>, 3, W>}},
 
 static const Variant g_variants[] = {SWE_TILE_LIST(SWE_VARIANT)};
 

@@ -67,7 +67,7 @@ int stats_from_dev(const Geo &g, const DevScen &ds, swe_stats *st);
 
 // ---- tile variants -------------------------------------------------------
 struct Variant {
-    int tx, ty, r, nt;
+    int tx, ty, r, nt, waves;
     size_t lds_bytes;
     void (*stage[3])(Geo, int, int);  // single-scenario stage kernels
 };

@@ -117,13 +117,14 @@ __device__ __forceinline__ float wt(float beta12, float kd, float ek)
 
 // One sweep along x (DIR 0) or y (DIR 1) over R cells.  li0 is the LDS index
 // of the window cell 3 before the first cell, st the LDS step between cells.
-// res[k][m] receives the sweep's part of L for cell k: -(Fhat_{k+1/2} -
-// Fhat_{k-1/2})/ds, plus the bed term -g (h+b)(bhat_{k+1/2} - bhat_{k-1/2})/ds
-// on the momentum component normal to the faces.
-template <int R, int DIR>
+// emit(k, L0, L1, L2) receives, as soon as cell k's second face completes,
+// the sweep's part of L for that cell: -(Fhat_{k+1/2} - Fhat_{k-1/2})/ds, plus
+// the bed term -g (h+b)(bhat_{k+1/2} - bhat_{k-1/2})/ds on the momentum
+// component normal to the faces.
+template <int R, int DIR, class Emit>
 __device__ __forceinline__ void sweep(const float *__restrict__ Lh, const float *__restrict__ Lhu,
                                       const float *__restrict__ Lhv, const float *__restrict__ Lb,
-                                      int li0, int st, const SweepK &K, float res[R][3])
+                                      int li0, int st, const SweepK &K, Emit &&emit)
 {
     constexpr int NF = R + 1;                 // faces k-1/2 for k = 0..R
     constexpr int MB = DIR == 0 ? 1 : 2;      // component whose weights reconstruct b
@@ -271,9 +272,11 @@ __device__ __forceinline__ void sweep(const float *__restrict__ Lh, const float 
             const float bh = 0.5f * fmaf(nbp[f], rp_b, nbm[f] * rm_b);
             if (f >= 1) {
                 const int k = f - 1;
+                float r3[3];
 #pragma unroll
-                for (int m = 0; m < 3; ++m) res[k][m] = (fprev[m] - Fh[m]) * K.inv_ds;
-                res[k][MB] = fmaf(-K.g * eta[k], (bh - bprev) * K.inv_ds, res[k][MB]);
+                for (int m = 0; m < 3; ++m) r3[m] = (fprev[m] - Fh[m]) * K.inv_ds;
+                r3[MB] = fmaf(-K.g * eta[k], (bh - bprev) * K.inv_ds, r3[MB]);
+                emit(k, r3[0], r3[1], r3[2]);
             }
 #pragma unroll
             for (int m = 0; m < 3; ++m) fprev[m] = Fh[m];
@@ -349,53 +352,60 @@ __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *
     const float kcap = (G.kappa_cap > 0.f && dt > 0.f) ? G.kappa_cap / dt : 3.0e38f;
 
     // ---- 1. stage the input tile and its cross-shaped halo in LDS ----------
-    for (int e = tid; e < C::WX * C::WY; e += NT) {
-        const int r = e / C::WX;
-        const int cc = e - r * C::WX;
-        const bool hx = cc < HALO || cc >= TX + HALO;
-        const bool hy = r < HALO || r >= TY + HALO;
-        if (hx && hy) continue;  // tile corners are never read
-        const int gx = x0 - HALO + cc, gy = y0 - HALO + r;
-        const bool inx = (unsigned)gx < (unsigned)nx, iny = (unsigned)gy < (unsigned)ny;
-        float h = 0.f, hu = 0.f, hv = 0.f, b = 0.f;
-        if (inx && iny) {
-            const int i = gy * pitch + gx;
-            h = w0[i];
-            hu = w1[i];
-            hv = w2[i];
-            b = G.b[i];
-        } else if (inx != iny) {
-            int side = -1, layer = 0, pos = 0, sx = gx, sy = gy;
-            if (!inx) {
-                if (gx < 0 && gx >= -HALO) { side = 0; layer = -1 - gx; sx = layer; }
-                else if (gx >= nx && gx < nx + HALO) { side = 1; layer = gx - nx; sx = nx - 1 - layer; }
-                pos = gy;
-            } else {
-                if (gy < 0 && gy >= -HALO) { side = 2; layer = -1 - gy; sy = layer; }
-                else if (gy >= ny && gy < ny + HALO) { side = 3; layer = gy - ny; sy = ny - 1 - layer; }
-                pos = gx;
-            }
-            if (side >= 0) {
-                if (G.bc[side] == BC_REFLECT) {
-                    const int i = sy * pitch + sx;
-                    h = w0[i];
-                    hu = w1[i];
-                    hv = w2[i];
-                    b = G.b[i];
-                    if (side < 2) hu = -hu; else hv = -hv;
-                } else {
+    // All loads are issued before any LDS store.  Ghost cells of mirrored
+    // sides read the mirror cell (normal momentum negated); indices are
+    // clamped into the grid, so the cells beyond three ghost layers that
+    // only ragged tail tiles touch read finite values whose results are
+    // discarded.  Frozen (FIXED) sides overwrite their ghosts afterwards.
+    {
+        constexpr int NE = C::WX * C::WY;
+        constexpr int IT = (NE + NT - 1) / NT;
+        float vh[IT], vhu[IT], vhv[IT], vb[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = tid + it * NT;
+            const int r = e / C::WX;
+            const int cc = e - r * C::WX;
+            const int gx = x0 - HALO + cc, gy = y0 - HALO + r;
+            int mx = gx < 0 ? -1 - gx : (gx >= nx ? 2 * nx - 1 - gx : gx);
+            int my = gy < 0 ? -1 - gy : (gy >= ny ? 2 * ny - 1 - gy : gy);
+            mx = mx < 0 ? 0 : (mx >= nx ? nx - 1 : mx);
+            my = my < 0 ? 0 : (my >= ny ? ny - 1 : my);
+            const int i = my * pitch + mx;
+            vh[it] = w0[i];
+            vhu[it] = w1[i];
+            vhv[it] = w2[i];
+            vb[it] = G.b[i];
+        }
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = tid + it * NT;
+            if (IT * NT != NE && e >= NE) break;
+            const int r = e / C::WX;
+            const int cc = e - r * C::WX;
+            const int gx = x0 - HALO + cc, gy = y0 - HALO + r;
+            const bool inx = (unsigned)gx < (unsigned)nx, iny = (unsigned)gy < (unsigned)ny;
+            float h = vh[it], hu = vhu[it], hv = vhv[it], b = vb[it];
+            if (!inx) hu = -hu;
+            if (!iny) hv = -hv;
+            if (inx != iny) {
+                // a ghost of exactly one side: frozen values if that side is FIXED
+                const int side = !inx ? (gx < 0 ? 0 : 1) : (gy < 0 ? 2 : 3);
+                const int layer = !inx ? (gx < 0 ? -1 - gx : gx - nx) : (gy < 0 ? -1 - gy : gy - ny);
+                if (G.bc[side] == BC_FIXED && layer < HALO) {
+                    const int pos = side < 2 ? gy : gx;
                     h = G.ghost[ghost_index(G, side, 0, layer, pos)];
                     hu = G.ghost[ghost_index(G, side, 1, layer, pos)];
                     hv = G.ghost[ghost_index(G, side, 2, layer, pos)];
                     b = G.ghost[ghost_index(G, side, 3, layer, pos)];
                 }
             }
+            const int li = r * C::SX + cc;
+            Lh[li] = h;
+            Lhu[li] = hu;
+            Lhv[li] = hv;
+            Lb[li] = b;
         }
-        const int li = r * C::SX + cc;
-        Lh[li] = h;
-        Lhu[li] = hu;
-        Lhv[li] = hv;
-        Lb[li] = b;
     }
     __syncthreads();
 
@@ -412,12 +422,13 @@ __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *
         const int row = tid % TY, seg = tid / TY;
         K.ha = 0.5f * ax;
         K.inv_ds = G.inv_dx;
-        float res[R][3];
-        sweep<R, 0>(Lh, Lhu, Lhv, Lb, (row + HALO) * C::SX + seg * R, 1, K, res);
-#pragma unroll
-        for (int k = 0; k < R; ++k)
-#pragma unroll
-            for (int m = 0; m < 3; ++m) Xr[m * C::XPLANE + row * C::XR + seg * R + k] = res[k][m];
+        float *xo = Xr + row * C::XR + seg * R;
+        sweep<R, 0>(Lh, Lhu, Lhv, Lb, (row + HALO) * C::SX + seg * R, 1, K,
+                    [&](int k, float l0, float l1, float l2) {
+                        xo[k] = l0;
+                        xo[C::XPLANE + k] = l1;
+                        xo[2 * C::XPLANE + k] = l2;
+                    });
     }
     __syncthreads();
 
@@ -427,7 +438,12 @@ __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *
     float res[R][3];
     K.ha = 0.5f * ay;
     K.inv_ds = G.inv_dy;
-    sweep<R, 1>(Lh, Lhu, Lhv, Lb, (seg * R) * C::SX + col + HALO, C::SX, K, res);
+    sweep<R, 1>(Lh, Lhu, Lhv, Lb, (seg * R) * C::SX + col + HALO, C::SX, K,
+                [&](int k, float l0, float l1, float l2) {
+                    res[k][0] = l0;
+                    res[k][1] = l1;
+                    res[k][2] = l2;
+                });
 
     unsigned int sxb = 0, syb = 0, rub = 0;
     float deficit = 0.f;
