@@ -9,10 +9,11 @@
 //
 // PERSISTENT mode: one kernel for the whole run.  Tiles are numbered round
 // after round ("tickets"); each block repeatedly takes the next group of
-// tickets with one atomic, maps a ticket to (round, scenario, tile) by binary
-// search in two small tables, waits until every tile of the scenario's
-// previous round has completed (per-scenario counter, acquire at agent
-// scope), runs the stage on the tile, and bumps the counter (release).  A
+// tickets with one atomic and maps them to (round, scenario, tile) by binary
+// search in two small tables.  The group is handled in runs that stay inside
+// one round: a run waits until every tile of the previous round of each
+// scenario it touches has completed (per-scenario counters, one acquire at
+// agent scope), runs its tiles, and publishes them with one release.  A
 // ticket only ever waits on smaller tickets, and tickets are taken by running
 // blocks, so the smallest unfinished ticket can always proceed: the kernel
 // cannot deadlock and needs no co-residency guarantee.
@@ -79,38 +80,48 @@ __global__ __launch_bounds__(C::NT, W) void k_persistent(BatchTables T)
         __syncthreads();
         if (t0 >= total) break;
         const long long t1 = t0 + T.group < total ? t0 + T.group : total;
-        // locate the first ticket of the group; later ones step forward
         int r = upper_index(T.rstart, T.nrounds, t0);
-        int l = (int)(t0 - T.rstart[r]);
-        int nr = T.ractive[r];
-        int slot = upper_index(T.prefix, nr, l);
-        for (long long t = t0; t < t1; ++t) {
-            if (t >= T.rstart[r + 1]) {  // next round
-                ++r;
-                l = 0;
-                slot = 0;
-                nr = T.ractive[r];
-            }
-            while (l >= T.prefix[slot + 1]) ++slot;
-            const int tl = l - T.prefix[slot];
-            const int ntx = T.ntx[slot];
-            const int ntiles = T.prefix[slot + 1] - T.prefix[slot];
-            const Geo &G = T.geo[T.order[slot]];
-            // every tile of this scenario's previous round must be complete;
-            // one wave waits and acquires, the barrier orders the others
+        long long t = t0;
+        // The grabbed tickets are handled in runs that stay inside one round.
+        // Tiles of one round never depend on each other, so a run waits once
+        // (one acquire) for the previous round of every scenario it touches,
+        // runs its tiles, and publishes them with one release.
+        while (t < t1) {
+            const long long te = t1 < T.rstart[r + 1] ? t1 : T.rstart[r + 1];
+            const int l0 = (int)(t - T.rstart[r]), l1 = (int)(te - T.rstart[r]);
+            const int s0 = upper_index(T.prefix, T.ractive[r], l0);
+            const int s1 = upper_index(T.prefix, T.ractive[r], l1 - 1);
             if (threadIdx.x == 0) {
-                const unsigned int need = (unsigned int)ntiles * (unsigned int)r;
-                while (__hip_atomic_load(&T.done[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need)
-                    __builtin_amdgcn_s_sleep(1);
+                for (int sl = s0; sl <= s1; ++sl) {
+                    const unsigned int need = (unsigned int)(T.prefix[sl + 1] - T.prefix[sl]) * (unsigned int)r;
+                    while (__hip_atomic_load(&T.done[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need)
+                        __builtin_amdgcn_s_sleep(1);
+                }
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             __syncthreads();
-            stage_tile<C>(G, tl % ntx, tl / ntx, lds, r % 3 + 1);
+            int slot = s0;
+            for (int l = l0; l < l1; ++l) {
+                while (l >= T.prefix[slot + 1]) ++slot;
+                const int tl = l - T.prefix[slot];
+                const int ntx = T.ntx[slot];
+                stage_tile<C>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, r % 3 + 1);
+                __syncthreads();
+            }
+            // every wave makes its own stores visible at agent scope before
+            // the barrier; then one thread publishes the run
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();
-            if (threadIdx.x == 0)
-                __hip_atomic_fetch_add(&T.done[slot], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            ++l;
-            (void)nr;
+            if (threadIdx.x == 0) {
+                for (int sl = s0; sl <= s1; ++sl) {
+                    const int a = l0 > T.prefix[sl] ? l0 : T.prefix[sl];
+                    const int b = l1 < T.prefix[sl + 1] ? l1 : T.prefix[sl + 1];
+                    __hip_atomic_fetch_add(&T.done[sl], (unsigned int)(b - a), __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            t = te;
+            ++r;
         }
     }
 }
@@ -244,16 +255,22 @@ int SegmentLauncher::run(const std::vector<Geo> &geos, const std::vector<int> &k
     T.nrounds = nrounds;
     T.nact = nact;
     T.group = group;
+    int per_cu = 0;
+    if (mode == SWE_BATCH_PERSISTENT &&
+        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, K.persistent, v.nt, 0) != hipSuccess || per_cu <= 0))
+        per_cu = 1;
+    long long grid = (long long)(per_cu > 0 ? per_cu : 1) * cus;
+    if (grid > rstart[nrounds]) grid = rstart[nrounds];
+    if (group <= 0) {
+        // about one run of tickets per block and round: one acquire and one
+        // release per block per round, as many as a kernel boundary costs
+        long long g = prefix[nact] / grid;
+        T.group = (int)(g < 4 ? 4 : (g > 64 ? 64 : g));
+    }
 
     auto enqueue = [&]() -> int {
         if (mode == SWE_BATCH_PERSISTENT) {
             hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(256), 0, stream, T.done, nact, T.ticket);
-            int per_cu = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, K.persistent, v.nt, 0) != hipSuccess ||
-                per_cu <= 0)
-                per_cu = 1;
-            long long grid = (long long)per_cu * cus;
-            if (grid > rstart[nrounds]) grid = rstart[nrounds];
             hipLaunchKernelGGL(K.persistent, dim3((unsigned)grid), dim3(v.nt), 0, stream, T);
         } else {
             for (int r = 0; r < nrounds; ++r) {

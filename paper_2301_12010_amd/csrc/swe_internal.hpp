@@ -89,7 +89,7 @@ struct SegmentLauncher {
     std::vector<char> hbuf;
     hipGraphExec_t graph = nullptr;
     int cus = 0;
-    int group = 8;  // tickets taken per atomic in persistent mode
+    int group = 0;  // tickets taken per atomic in persistent mode (0: automatic)
     ~SegmentLauncher();
     int run(const std::vector<Geo> &geos, const std::vector<int> &ksteps, int vi, int mode, bool use_graph,
             hipStream_t stream);
