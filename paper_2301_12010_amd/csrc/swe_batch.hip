@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "swe_internal.hpp"
+#include "swe_schedule.hpp"
 
 namespace swe {
 
@@ -176,32 +177,16 @@ int SegmentLauncher::run(const std::vector<Geo> &geos, const std::vector<int> &k
     const Variant &v = variant(vi);
     const BatchKernels &K = g_bk[vi];
     const int n = (int)geos.size();
-    std::vector<int> act;
-    for (int i = 0; i < n; ++i)
-        if (ksteps[i] > 0) act.push_back(i);
-    if (act.empty()) return SWE_OK;
-    std::stable_sort(act.begin(), act.end(), [&](int a, int b) { return ksteps[a] > ksteps[b]; });
-    const int nact = (int)act.size();
-    const int nrounds = 3 * ksteps[act[0]];
-
-    std::vector<int> prefix(nact + 1, 0), ntx(nact), order(nact);
-    for (int q = 0; q < nact; ++q) {
-        const Geo &g = geos[act[q]];
-        const int tx = (g.nx + v.tx - 1) / v.tx, ty = (g.ny + v.ty - 1) / v.ty;
-        ntx[q] = tx;
-        order[q] = act[q];
-        prefix[q + 1] = prefix[q] + tx * ty;
+    std::vector<int> nxs(n), nys(n);
+    for (int i = 0; i < n; ++i) {
+        nxs[i] = geos[i].nx;
+        nys[i] = geos[i].ny;
     }
-    std::vector<int> ractive(nrounds);
-    std::vector<long long> rstart(nrounds + 1, 0);
-    {
-        int a = nact;
-        for (int r = 0; r < nrounds; ++r) {
-            while (a > 0 && 3 * ksteps[act[a - 1]] <= r) --a;
-            ractive[r] = a;
-            rstart[r + 1] = rstart[r] + prefix[a];
-        }
-    }
+    const Schedule S = build_schedule(nxs, nys, ksteps, v.tx, v.ty);
+    if (S.nact == 0) return SWE_OK;
+    const int nact = S.nact, nrounds = S.nrounds;
+    const std::vector<int> &prefix = S.prefix, &ntx = S.ntx, &order = S.order, &ractive = S.ractive;
+    const std::vector<long long> &rstart = S.rstart;
 
     const size_t o_geo = 0, o_order = o_geo + al(n * sizeof(Geo));
     const size_t o_prefix = o_order + al(nact * sizeof(int));
@@ -261,12 +246,9 @@ int SegmentLauncher::run(const std::vector<Geo> &geos, const std::vector<int> &k
         per_cu = 1;
     long long grid = (long long)(per_cu > 0 ? per_cu : 1) * cus;
     if (grid > rstart[nrounds]) grid = rstart[nrounds];
-    if (group <= 0) {
-        // about one run of tickets per block and round: one acquire and one
-        // release per block per round, as many as a kernel boundary costs
-        long long g = prefix[nact] / grid;
-        T.group = (int)(g < 4 ? 4 : (g > 64 ? 64 : g));
-    }
+    // about one run of tickets per block and round: one acquire and one
+    // release per block per round, as many as a kernel boundary costs
+    if (group <= 0) T.group = ticket_group(S, grid);
 
     auto enqueue = [&]() -> int {
         if (mode == SWE_BATCH_PERSISTENT) {
