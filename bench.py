@@ -230,6 +230,82 @@ def run_serving(args, swe, members, capacity_per_s):
             "segments": st["segments"]}
 
 
+def run_uneven(args, torch, inputs, swe):
+    """Uneven batch: 200 scenarios of four grid sizes and U{1000..4000} steps."""
+    plan = inputs.uneven_plan(args.uneven_count)
+    t0 = time.perf_counter()
+    bt = swe.Batch()
+    cells_steps = 0
+    by_size = {}
+    for s_idx, ((nx, ny), steps) in enumerate(plan):
+        sc = inputs.uneven_scenario(s_idx, plan)
+        bt.add_scenario(sc)
+        cells_steps += nx * ny * steps
+        by_size.setdefault((nx, ny), []).append((s_idx, steps))
+        if s_idx % 20 == 0:
+            log(f"uneven: generated and uploaded {s_idx + 1}/{len(plan)}")
+    log(f"uneven: {len(plan)} scenarios ready in {time.perf_counter() - t0:.1f}s")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    bt.run()
+    for i in range(len(plan)):
+        st = bt.stats(i)
+        assert st["rc"] == 0 and st["step"] == plan[i][1], (i, st)
+    dt = time.perf_counter() - t
+    bt.close()
+    out = {"workload": f"uneven_batch_{len(plan)}", "scenarios": len(plan),
+           "cell_updates": cells_steps, "seconds": dt, "cell_updates_per_s": cells_steps / dt,
+           "scenarios_per_hour": len(plan) / dt * 3600.0,
+           "sizes": {f"{nx}x{ny}": len(v) for (nx, ny), v in by_size.items()}}
+    log(f"uneven batched: {dt:.1f}s, {cells_steps / dt:.3e} cell-updates/s")
+    # plain solver, one scenario at a time: two members of each size class,
+    # per-cell-update rate of the class applied to all of its members
+    plain_s = 0.0
+    for (nx, ny), members in by_size.items():
+        rates = []
+        for s_idx, steps in members[:2]:
+            sc = inputs.uneven_scenario(s_idx, plan)
+            sol = swe.Solver.from_scenario(sc)
+            sol.stats()
+            t = time.perf_counter()
+            sol.step(steps)
+            sol.stats()
+            rates.append(nx * ny * steps / (time.perf_counter() - t))
+            sol.close()
+        rate = sum(rates) / len(rates)
+        plain_s += sum(nx * ny * st / rate for _, st in members)
+        out.setdefault("plain_rate_by_size", {})[f"{nx}x{ny}"] = rate
+    out["plain_solver_seconds_est"] = plain_s
+    out["plain_solver_scenarios_per_hour"] = len(plan) / plain_s * 3600.0
+    out["batched_over_plain"] = out["scenarios_per_hour"] / out["plain_solver_scenarios_per_hour"]
+    return out
+
+
+def run_serving_scale(args, torch, inputs, swe):
+    members = inputs.mitigation_ensemble(args.ens_count, 1024, 1024, 3000)
+    # capacity: a batch of the same size mix and steps, as in the ensemble run
+    bt = swe.Batch()
+    for sc in members:
+        bt.add_scenario(sc, 300)
+    bt.run(20)
+    bt.stats(0)
+    t = time.perf_counter()
+    bt.run()
+    bt.stats(0)
+    dt = time.perf_counter() - t
+    bt.close()
+    cap = len(members) * 280 / dt  # scenario-steps per second / steps
+    out = {"capacity_scenario_steps_per_s": cap}
+    for frac in args.serve_loads:
+        a = argparse.Namespace(**vars(args))
+        a.ens_steps = 1
+        res = run_serving(a, swe, members, cap * frac / 0.7)
+        res["load_fraction"] = frac
+        out[f"load_{frac}"] = res
+        log(f"serving at {frac}: p50 {res['p50_time_to_result_s']:.2f}s p99 {res['p99_time_to_result_s']:.2f}s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +323,11 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-steps", type=int, default=1000)
     ap.add_argument("--serve-budget-gb", type=int, default=2)
+    ap.add_argument("--workload", choices=("coast", "uneven", "serving"), default="coast",
+                    help="coast: the main line (default); uneven: the 200-scenario uneven batch; "
+                         "serving: Poisson serving at --serve-loads of capacity")
+    ap.add_argument("--uneven-count", type=int, default=200)
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.7, 1.0])
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -260,6 +341,12 @@ def main():
     from paper_2301_12010_amd import inputs, swe
 
     torch.cuda.set_device(0)
+    if args.workload == "uneven":
+        print(json.dumps(run_uneven(args, torch, inputs, swe)), flush=True)
+        return
+    if args.workload == "serving":
+        print(json.dumps(run_serving_scale(args, torch, inputs, swe)), flush=True)
+        return
     sc, value, ms, roofline, other, tv = run_large(args, torch, inputs, swe)
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1,

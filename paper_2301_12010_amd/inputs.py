@@ -348,3 +348,45 @@ def mirror_x(sc: Scenario) -> Scenario:
     M = lambda a: np.ascontiguousarray(a[:, ::-1])
     return Scenario(sc.name + "_M", q, M(sc.b), M(sc.n), M(sc.h), -M(sc.hu), M(sc.hv),
                     sc.nsteps, dict(sc.meta))
+
+
+def nwave_surface(dist_offshore, A: float = 15.0, lam: float = 2000.0, origin: float = 1000.0):
+    """Carrier's N-wave surface (Section 2.4, Eq. (20)) at a distance from
+    the shoreline: eta = 2 (a1 exp(-k1 (x - x1)^2) - a2 exp(-k2 (x - x2)^2))
+    with x1 = origin + 0.5151125 lam, x2 = origin + 0.2048 lam,
+    k1 = 28.416/lam^2, k2 = 256/lam^2, a1 = A, a2 = A/3.  The printed
+    second exponent lacks its minus sign; it is read as -k2 (a decaying
+    trough)."""
+    x = np.asarray(dist_offshore, dtype=np.float64)
+    x1, x2 = origin + 0.5151125 * lam, origin + 0.2048 * lam
+    k1, k2 = 28.416 / lam ** 2, 256.0 / lam ** 2
+    a1, a2 = A, A / 3.0
+    return 2.0 * (a1 * np.exp(-k1 * (x - x1) ** 2) - a2 * np.exp(-k2 * (x - x2) ** 2))
+
+
+def nwave_beach(nx: int = 2048, ny: int = 256, dx: float = 2.0, A: float = 15.0,
+                lam: float = 2000.0, slope: float = 0.1, hill: bool = True,
+                hill_height: float = 8.0, hill_radius=(60.0, 25.0), seed: int = 3,
+                manning: float = 0.025, nsteps: int = 0) -> Scenario:
+    """Planar beach with a coastal hill hit by Carrier's N-wave (Section 2.4).
+
+    The still shoreline sits at 0.8 Lx with the sea to the west; the bed rises
+    with ``slope`` (1/10 as in the planar-beach benchmark) and is clamped at
+    +20 m.  An elliptical Gaussian hill (radii along x and y) stands on the
+    shoreline at a seeded y position.  The N-wave is placed with the
+    printed origin of 1000 m offshore; momentum starts at zero.  Free-slip
+    walls on all sides.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X, Y = _centres(nx, ny, dx, dx)
+    Lx, Ly = nx * dx, ny * dx
+    xs = 0.8 * Lx
+    b = np.clip((X - xs) * slope, -1e9, 20.0)
+    if hill:
+        cy = rng.uniform(0.3, 0.7) * Ly
+        b = b + hill_height * np.exp(-(((X - xs) / hill_radius[0]) ** 2 + ((Y - cy) / hill_radius[1]) ** 2))
+    eta = nwave_surface(xs - X, A, lam)
+    h, hu, hv = _wet_state(eta, b, 1e-3)
+    p = Params(nx, ny, dx, dx, cfl=0.4, h_dry=1e-3, kappa_cap=1.0)
+    return Scenario(f"nwave_beach_{nx}x{ny}", p, _f32(b), _f32(np.full((ny, nx), manning)),
+                    _f32(h), _f32(hu), _f32(hv), nsteps, dict(xs=xs, A=A, lam=lam))

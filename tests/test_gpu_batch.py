@@ -132,7 +132,7 @@ def test_uneven_batch_full_sizes_truncated():
     for i, (sc, n) in enumerate(zip(scen, steps)):
         g = bt.read(i)
         assert g[3]["step"] == n
-        ref = alone(sc, n, swe_default_tile(bt))
+        ref = alone(sc, n, 1)  # every tile variant gives the same state
         for a, b in zip(g[:3], ref[:3]):
             assert np.array_equal(a, b), sc.name
     # the smallest member against the checker
@@ -144,7 +144,22 @@ def test_uneven_batch_full_sizes_truncated():
     bt.close()
 
 
-def swe_default_tile(bt):
-    # automatic choice: the library's default for the largest member; any
-    # variant gives the same state, so variant 1 is as good a reference
-    return 1
+def test_nwave_beach_with_hill_against_checker():
+    # Carrier N-wave on a 1/10 beach with a coastal hill (Section 2.4), in a
+    # batch with a hill-less twin: batched == alone, and against the checker
+    sc = inputs.nwave_beach(nx=1024, ny=96, dx=4.0)
+    twin = inputs.nwave_beach(nx=1024, ny=96, dx=4.0, hill=False)
+    bt = swe.Batch()
+    bt.add_scenario(sc, 40)
+    bt.add_scenario(twin, 40)
+    bt.run()
+    g = bt.read(0)
+    ref = alone(sc, 40, 4)
+    for a, b in zip(g[:3], ref[:3]):
+        assert np.array_equal(a, b)
+    o = oracle.Oracle.from_scenario(sc)
+    o.step(40)
+    e_h, e_hu, e_hv, dm, frac = front_split_errors(g, o.state())
+    say("nwave", e_h, e_hu, e_hv, dm, frac, g[3]["runup"], o.scalars()["runup"])
+    assert max(e_h, e_hu, e_hv) <= TOL_SHOCK and dm <= 5e-3
+    bt.close()

@@ -63,3 +63,21 @@ def test_uneven_plan_shape():
     assert len(plan) == 200
     assert {s for s, _ in plan} <= set(inputs.UNEVEN_SIZES)
     assert all(1000 <= n <= 4000 for _, n in plan)
+
+
+def test_nwave_shape_follows_section_2_4():
+    import json
+    c = json.load(open(os.path.join(GOLD, "paper_constants.json")))["nwave"]
+    lam, A = c["lambda"], c["A"]
+    x1 = 1000 + c["x1_factor"] * lam
+    x2 = 1000 + c["x2_factor"] * lam
+    x = np.linspace(0, 6000, 60001)
+    eta = inputs.nwave_surface(x, A, lam)
+    # crest near x1 of height ~2 a1, trough near x2 of depth ~2 a2: the second
+    # exponent decays (read with its minus sign)
+    i_max, i_min = np.argmax(eta), np.argmin(eta)
+    assert abs(x[i_max] - x1) < 0.05 * lam and abs(eta[i_max] - 2 * A) < 0.05 * 2 * A
+    assert abs(x[i_min] - x2) < 0.05 * lam and eta[i_min] < -0.5 * 2 * A * c["a2_over_a1"]
+    assert abs(eta[0]) < 1e-3 and abs(eta[-1]) < 1e-3
+    sc = inputs.nwave_beach(nx=512, ny=32, dx=8.0)
+    assert np.all(sc.h >= 0) and sc.b.max() <= 20 + 8 + 1e-4
