@@ -106,7 +106,7 @@ __global__ __launch_bounds__(C::NT, W) void k_persistent(BatchTables T)
                 while (l >= T.prefix[slot + 1]) ++slot;
                 const int tl = l - T.prefix[slot];
                 const int ntx = T.ntx[slot];
-                stage_tile<C>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, r % 3 + 1);
+                stage_tile<C, false>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, r % 3 + 1);
                 __syncthreads();
             }
             // every wave makes its own stores visible at agent scope before
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(C::NT, W) void k_round(BatchTables T, int nact_roun
     const int slot = upper_index(T.prefix, nact_round, id);
     const int tl = id - T.prefix[slot];
     const int ntx = T.ntx[slot];
-    stage_tile<C>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, S);
+    stage_tile<C, (W <= 2)>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, S);
 }
 
 // Clears the run's counters (a kernel, so graph replays need no memset node).
@@ -158,7 +158,7 @@ struct BatchKernels {
 // same order as the single-scenario variant table
 static const BatchKernels g_bk[] = {SWE_BK(64, 16, 8, 2) SWE_BK(64, 32, 8, 2) SWE_BK(32, 32, 8, 2)
                                         SWE_BK(64, 16, 4, 2) SWE_BK(128, 16, 8, 2) SWE_BK(64, 16, 4, 3)
-                                            SWE_BK(32, 32, 4, 3) SWE_BK(32, 32, 4, 4)};
+                                            SWE_BK(32, 32, 4, 3)};
 
 // ---------------------------------------------------------------------------
 // segment launcher (shared by swe_batch and the server)

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(C::NT, W) void k_stage(Geo G, int ntx, int nblocks)
 {
     __shared__ float lds[C::LDS_FLOATS];
     const int id = xcd_remap(blockIdx.x, nblocks);
-    stage_tile<C>(G, id % ntx, id / ntx, lds, S);
+    stage_tile<C, (W <= 2)>(G, id % ntx, id / ntx, lds, S);
 }
 
 // Wave speeds (slot 0) and runup of the initial state.
@@ -129,10 +129,9 @@ int launch_mass(const Geo &g, hipStream_t stream)
     X(64, 16, 4, 2)      \
     X(128, 16, 8, 2)     \
     X(64, 16, 4, 3)      \
-    X(32, 32, 4, 3)      \
-    X(32, 32, 4, 4)
+    X(32, 32, 4, 3)
 
-#define SWE_VARIANT(TX, TY, R, W)                                                         \
+#define SWE_VARIANT(TX, TY, R, W)                                                           \
     {TX, TY, R, TileCfg<TX, TY, R>::NT, W, sizeof(float) * TileCfg<TX, TY, R>::LDS_FLOATS, \
      {k_stage<TileCfg<TX, TY, R>, 1, W>, k_stage<TileCfg<TX, TY, R>, 2, W>, k_stage<TileCfg<TX, TY, R>, 3, W>}},
 

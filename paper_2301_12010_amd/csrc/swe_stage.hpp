@@ -317,97 +317,137 @@ __device__ __forceinline__ unsigned int speed_bits(float s)
 // ---------------------------------------------------------------------------
 // STAGE 1: w = u^n -> A;  2: w = A -> B;  3: w = B -> u^n (in place: each
 // cell of u^n is read and then written by the same thread, and no halo of
-// stage 3 reads u^n).
-template <class C>
-__device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *lds, const int STAGE)
+// stage 3 reads u^n).  A tile is processed in four parts: tile_load (every
+// global load of the tile in flight at once, into registers), tile_store
+// (registers -> LDS), tile_compute (sweeps, sources, RK combination, store;
+// per-thread partials) and stage_publish (block reduction, at most one
+// atomic per quantity).
+
+// Per-stage scalars, identical in every block.
+struct StageScalars {
+    int stage;
+    float ax, ay, dt, kcap;
+};
+
+__device__ __forceinline__ StageScalars stage_scalars(const Geo &G, int STAGE)
 {
-    constexpr int TX = C::TX, TY = C::TY, R = C::R, NT = C::NT;
+    StageScalars sc;
+    DevScen *sd = G.sd;
+    sc.stage = STAGE;
+    sc.ax = __uint_as_float(__hip_atomic_load(&sd->alpha[STAGE - 1][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    sc.ay = __uint_as_float(__hip_atomic_load(&sd->alpha[STAGE - 1][1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (STAGE == 1) {
+        if (G.cfl > 0.f) {
+            const double den = (double)sc.ax * (double)G.inv_dx + (double)sc.ay * (double)G.inv_dy;
+            sc.dt = (den > 0.0 && den < 1e300) ? (float)((double)G.cfl / den) : 0.f;
+        } else {
+            sc.dt = G.dt_fixed;
+        }
+    } else {
+        sc.dt = __hip_atomic_load(&sd->dt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    sc.kcap = (G.kappa_cap > 0.f && sc.dt > 0.f) ? G.kappa_cap / sc.dt : 3.0e38f;
+    return sc;
+}
+
+// Per-thread partial reductions of a stage.
+struct StagePartials {
+    unsigned int sxb = 0, syb = 0, rub = 0;
+    float deficit = 0.f;
+};
+
+template <class C>
+struct TileRegs {
+    static constexpr int NE = C::WX * C::WY;
+    static constexpr int IT = (NE + C::NT - 1) / C::NT;
+    float h[IT], hu[IT], hv[IT], b[IT];
+};
+
+// Global loads of a tile and its halo.  Ghost cells of mirrored sides read
+// the mirror cell; indices are clamped into the grid, so the cells beyond
+// three ghost layers that only ragged tail tiles touch read finite values
+// whose results are discarded.  All loads are issued back to back.
+template <class C>
+__device__ __forceinline__ void tile_load(const Geo &G, int STAGE, int tx, int ty, TileRegs<C> &v)
+{
+    const float *const *W = STAGE == 1 ? G.U : STAGE == 2 ? G.A : G.B;
+    const float *w0 = W[0], *w1 = W[1], *w2 = W[2];
+    const int nx = G.nx, ny = G.ny, pitch = G.pitch;
+    const int x0 = tx * C::TX, y0 = ty * C::TY;
+#pragma unroll
+    for (int it = 0; it < TileRegs<C>::IT; ++it) {
+        const int e = threadIdx.x + it * C::NT;
+        const int r = e / C::WX;
+        const int cc = e - r * C::WX;
+        const int gx = x0 - HALO + cc, gy = y0 - HALO + r;
+        int mx = gx < 0 ? -1 - gx : (gx >= nx ? 2 * nx - 1 - gx : gx);
+        int my = gy < 0 ? -1 - gy : (gy >= ny ? 2 * ny - 1 - gy : gy);
+        mx = mx < 0 ? 0 : (mx >= nx ? nx - 1 : mx);
+        my = my < 0 ? 0 : (my >= ny ? ny - 1 : my);
+        const int i = my * pitch + mx;
+        v.h[it] = w0[i];
+        v.hu[it] = w1[i];
+        v.hv[it] = w2[i];
+        v.b[it] = G.b[i];
+    }
+}
+
+// LDS stores of a loaded tile: normal momentum negated on mirrored ghosts,
+// frozen values on FIXED sides.
+template <class C>
+__device__ __forceinline__ void tile_store(const Geo &G, int tx, int ty, const TileRegs<C> &v, float *lds)
+{
     float *Lh = lds, *Lhu = lds + C::PLANE, *Lhv = lds + 2 * C::PLANE, *Lb = lds + 3 * C::PLANE;
+    const int nx = G.nx, ny = G.ny;
+    const int x0 = tx * C::TX, y0 = ty * C::TY;
+    constexpr int NE = TileRegs<C>::NE, IT = TileRegs<C>::IT;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = threadIdx.x + it * C::NT;
+        if (IT * C::NT != NE && e >= NE) break;
+        const int r = e / C::WX;
+        const int cc = e - r * C::WX;
+        const int gx = x0 - HALO + cc, gy = y0 - HALO + r;
+        const bool inx = (unsigned)gx < (unsigned)nx, iny = (unsigned)gy < (unsigned)ny;
+        float h = v.h[it], hu = v.hu[it], hv = v.hv[it], b = v.b[it];
+        if (!inx) hu = -hu;
+        if (!iny) hv = -hv;
+        if (inx != iny) {
+            // a ghost of exactly one side: frozen values if that side is FIXED
+            const int side = !inx ? (gx < 0 ? 0 : 1) : (gy < 0 ? 2 : 3);
+            const int layer = !inx ? (gx < 0 ? -1 - gx : gx - nx) : (gy < 0 ? -1 - gy : gy - ny);
+            if (G.bc[side] == BC_FIXED && layer < HALO) {
+                const int pos = side < 2 ? gy : gx;
+                h = G.ghost[ghost_index(G, side, 0, layer, pos)];
+                hu = G.ghost[ghost_index(G, side, 1, layer, pos)];
+                hv = G.ghost[ghost_index(G, side, 2, layer, pos)];
+                b = G.ghost[ghost_index(G, side, 3, layer, pos)];
+            }
+        }
+        const int li = r * C::SX + cc;
+        Lh[li] = h;
+        Lhu[li] = hu;
+        Lhv[li] = hv;
+        Lb[li] = b;
+    }
+}
+
+// Sweeps, sources, RK combination and store of a tile staged in LDS.  Ends
+// with the LDS tile still in use: the caller synchronises before overwriting
+// it.  PF: issue the combination's global reads before the y sweep (costs
+// 4R registers across it; off for variants whose register budget is tight).
+template <class C, bool PF>
+__device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &sc, int tx, int ty, float *lds,
+                                             StagePartials &acc)
+{
+    constexpr int TX = C::TX, TY = C::TY, R = C::R;
+    const int STAGE = sc.stage;
+    const float *Lh = lds, *Lhu = lds + C::PLANE, *Lhv = lds + 2 * C::PLANE, *Lb = lds + 3 * C::PLANE;
     float *Xr = lds + 4 * C::PLANE;
     const int tid = threadIdx.x;
     const int x0 = tx * TX, y0 = ty * TY;
     const int nx = G.nx, ny = G.ny, pitch = G.pitch;
-    DevScen *sd = G.sd;
-
-    const float *const *W = STAGE == 1 ? G.U : STAGE == 2 ? G.A : G.B;
     float *const *O = STAGE == 1 ? G.A : STAGE == 2 ? G.B : G.U;
-    const float *w0 = W[0], *w1 = W[1], *w2 = W[2];
-
-    // ---- stage scalars ------------------------------------------------------
-    const float ax = __uint_as_float(__hip_atomic_load(&sd->alpha[STAGE - 1][0], __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT));
-    const float ay = __uint_as_float(__hip_atomic_load(&sd->alpha[STAGE - 1][1], __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT));
-    float dt;
-    if (STAGE == 1) {
-        if (G.cfl > 0.f) {
-            const double den = (double)ax * (double)G.inv_dx + (double)ay * (double)G.inv_dy;
-            dt = (den > 0.0 && den < 1e300) ? (float)((double)G.cfl / den) : 0.f;
-        } else {
-            dt = G.dt_fixed;
-        }
-    } else {
-        dt = __hip_atomic_load(&sd->dt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    const float kcap = (G.kappa_cap > 0.f && dt > 0.f) ? G.kappa_cap / dt : 3.0e38f;
-
-    // ---- 1. stage the input tile and its cross-shaped halo in LDS ----------
-    // All loads are issued before any LDS store.  Ghost cells of mirrored
-    // sides read the mirror cell (normal momentum negated); indices are
-    // clamped into the grid, so the cells beyond three ghost layers that
-    // only ragged tail tiles touch read finite values whose results are
-    // discarded.  Frozen (FIXED) sides overwrite their ghosts afterwards.
-    {
-        constexpr int NE = C::WX * C::WY;
-        constexpr int IT = (NE + NT - 1) / NT;
-        float vh[IT], vhu[IT], vhv[IT], vb[IT];
-#pragma unroll
-        for (int it = 0; it < IT; ++it) {
-            const int e = tid + it * NT;
-            const int r = e / C::WX;
-            const int cc = e - r * C::WX;
-            const int gx = x0 - HALO + cc, gy = y0 - HALO + r;
-            int mx = gx < 0 ? -1 - gx : (gx >= nx ? 2 * nx - 1 - gx : gx);
-            int my = gy < 0 ? -1 - gy : (gy >= ny ? 2 * ny - 1 - gy : gy);
-            mx = mx < 0 ? 0 : (mx >= nx ? nx - 1 : mx);
-            my = my < 0 ? 0 : (my >= ny ? ny - 1 : my);
-            const int i = my * pitch + mx;
-            vh[it] = w0[i];
-            vhu[it] = w1[i];
-            vhv[it] = w2[i];
-            vb[it] = G.b[i];
-        }
-#pragma unroll
-        for (int it = 0; it < IT; ++it) {
-            const int e = tid + it * NT;
-            if (IT * NT != NE && e >= NE) break;
-            const int r = e / C::WX;
-            const int cc = e - r * C::WX;
-            const int gx = x0 - HALO + cc, gy = y0 - HALO + r;
-            const bool inx = (unsigned)gx < (unsigned)nx, iny = (unsigned)gy < (unsigned)ny;
-            float h = vh[it], hu = vhu[it], hv = vhv[it], b = vb[it];
-            if (!inx) hu = -hu;
-            if (!iny) hv = -hv;
-            if (inx != iny) {
-                // a ghost of exactly one side: frozen values if that side is FIXED
-                const int side = !inx ? (gx < 0 ? 0 : 1) : (gy < 0 ? 2 : 3);
-                const int layer = !inx ? (gx < 0 ? -1 - gx : gx - nx) : (gy < 0 ? -1 - gy : gy - ny);
-                if (G.bc[side] == BC_FIXED && layer < HALO) {
-                    const int pos = side < 2 ? gy : gx;
-                    h = G.ghost[ghost_index(G, side, 0, layer, pos)];
-                    hu = G.ghost[ghost_index(G, side, 1, layer, pos)];
-                    hv = G.ghost[ghost_index(G, side, 2, layer, pos)];
-                    b = G.ghost[ghost_index(G, side, 3, layer, pos)];
-                }
-            }
-            const int li = r * C::SX + cc;
-            Lh[li] = h;
-            Lhu[li] = hu;
-            Lhv[li] = hv;
-            Lb[li] = b;
-        }
-    }
-    __syncthreads();
 
     SweepK K;
     K.g = G.g;
@@ -417,10 +457,10 @@ __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *
     K.e1 = G.eps12 * KD1;
     K.e2 = G.eps12 * KD2;
 
-    // ---- 2. x sweep: thread -> (row, segment of R cells) -------------------
+    // ---- x sweep: thread -> (row, segment of R cells) ------------------------
     {
         const int row = tid % TY, seg = tid / TY;
-        K.ha = 0.5f * ax;
+        K.ha = 0.5f * sc.ax;
         K.inv_ds = G.inv_dx;
         float *xo = Xr + row * C::XR + seg * R;
         sweep<R, 0>(Lh, Lhu, Lhv, Lb, (row + HALO) * C::SX + seg * R, 1, K,
@@ -432,11 +472,29 @@ __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *
     }
     __syncthreads();
 
-    // ---- 3. y sweep, sources, RK combination, store, reductions -------------
+    // ---- y sweep, sources, RK combination, store ------------------------------
     const int col = tid % TX, seg = tid / TX;
     const int gx = x0 + col;
+    // the per-cell global reads of the combination (g n^2, and u^n in stages
+    // 2 and 3) are issued before the y sweep, so their latency hides behind
+    // it; indices are clamped into the grid (cells outside it are skipped)
+    float pgn2[R], pun[R][3];
+    if (PF) {
+        const int cx = gx < nx ? gx : nx - 1;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int gy = y0 + seg * R + k;
+            const int gi = (gy < ny ? gy : ny - 1) * pitch + cx;
+            pgn2[k] = G.gn2[gi];
+            if (STAGE != 1) {
+                pun[k][0] = G.U[0][gi];
+                pun[k][1] = G.U[1][gi];
+                pun[k][2] = G.U[2][gi];
+            }
+        }
+    }
     float res[R][3];
-    K.ha = 0.5f * ay;
+    K.ha = 0.5f * sc.ay;
     K.inv_ds = G.inv_dy;
     sweep<R, 1>(Lh, Lhu, Lhv, Lb, (seg * R) * C::SX + col + HALO, C::SX, K,
                 [&](int k, float l0, float l1, float l2) {
@@ -445,9 +503,7 @@ __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *
                     res[k][2] = l2;
                 });
 
-    unsigned int sxb = 0, syb = 0, rub = 0;
-    float deficit = 0.f;
-    const float h_dry = G.h_dry;
+    const float h_dry = G.h_dry, dt = sc.dt;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int ly = seg * R + k;
@@ -461,31 +517,33 @@ __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *
         float Lhu_ = Xr[C::XPLANE + xi] + res[k][1];
         float Lhv_ = Xr[2 * C::XPLANE + xi] + res[k][2];
         // explicit Manning friction, wet cells only, rate capped at kappa_cap/dt
-        const float gn2 = G.gn2[gi];
+        const float gn2 = PF ? pgn2[k] : G.gn2[gi];
         if (h > h_dry && gn2 > 0.f) {
             const float qn = sqrtf(fmaf(hu, hu, hv * hv));
             const float hm73 = __builtin_amdgcn_exp2f(-2.33333333333333f * __builtin_amdgcn_logf(h));
-            const float kap = fminf(gn2 * qn * hm73, kcap);
+            const float kap = fminf(gn2 * qn * hm73, sc.kcap);
             Lhu_ = fmaf(-kap, hu, Lhu_);
             Lhv_ = fmaf(-kap, hv, Lhv_);
         }
         float oh = fmaf(dt, Lh_, h), ohu = fmaf(dt, Lhu_, hu), ohv = fmaf(dt, Lhv_, hv);
         if (STAGE == 2) {
-            oh = fmaf(0.75f, G.U[0][gi], 0.25f * oh);
-            ohu = fmaf(0.75f, G.U[1][gi], 0.25f * ohu);
-            ohv = fmaf(0.75f, G.U[2][gi], 0.25f * ohv);
+            oh = fmaf(0.75f, PF ? pun[k][0] : G.U[0][gi], 0.25f * oh);
+            ohu = fmaf(0.75f, PF ? pun[k][1] : G.U[1][gi], 0.25f * ohu);
+            ohv = fmaf(0.75f, PF ? pun[k][2] : G.U[2][gi], 0.25f * ohv);
         }
         if (STAGE == 3) {
             // u^n + (2/3)(w + dt L - u^n): the FP32 weights 1/3 and 2/3 sum
             // to 1 + 3e-8, which would create mass every step; this form
             // keeps the two weights summing to exactly one
-            const float un0 = G.U[0][gi], un1 = G.U[1][gi], un2 = G.U[2][gi];
+            const float un0 = PF ? pun[k][0] : G.U[0][gi];
+            const float un1 = PF ? pun[k][1] : G.U[1][gi];
+            const float un2 = PF ? pun[k][2] : G.U[2][gi];
             oh = fmaf(2.f / 3.f, oh - un0, un0);
             ohu = fmaf(2.f / 3.f, ohu - un1, un1);
             ohv = fmaf(2.f / 3.f, ohv - un2, un2);
         }
         if (oh < 0.f) {
-            deficit -= oh;
+            acc.deficit -= oh;
             oh = 0.f;
         }
         const bool wet = oh > h_dry;
@@ -502,23 +560,34 @@ __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *
         const bool fin = fabsf(oh) <= 3.4e38f && fabsf(ohu) <= 3.4e38f && fabsf(ohv) <= 3.4e38f;
         const unsigned int bx = fin ? speed_bits(fabsf(ohu * inv) + cel) : 0x7f800000u;
         const unsigned int by = fin ? speed_bits(fabsf(ohv * inv) + cel) : 0x7f800000u;
-        sxb = bx > sxb ? bx : sxb;
-        syb = by > syb ? by : syb;
+        acc.sxb = bx > acc.sxb ? bx : acc.sxb;
+        acc.syb = by > acc.syb ? by : acc.syb;
         if (STAGE == 3) {
             const float bb = Lb[li];
             if (wet && bb > 0.f) {
                 const unsigned int u = __float_as_uint(bb);
-                rub = u > rub ? u : rub;
+                acc.rub = u > acc.rub ? u : acc.rub;
             }
         }
     }
+}
 
-    // ---- epilogue: block reductions ------------------------------------------
-    sxb = wave_max_u32(sxb);
-    syb = wave_max_u32(syb);
-    const bool any_def = __any(deficit > 0.f);
-    double dsum = any_def ? wave_sum_f64((double)deficit) : 0.0;
-    if (STAGE == 3) rub = wave_max_u32(rub);
+// Block reduction of the partials and the stage's atomics.  `first` marks
+// the block that processed tile (0, 0): it does the once-per-stage
+// bookkeeping.  Uses the first bytes of LDS; synchronises before and after.
+template <class C>
+__device__ __forceinline__ void stage_publish(const Geo &G, const StageScalars &sc, StagePartials acc, bool first,
+                                              float *lds)
+{
+    constexpr int NT = C::NT;
+    const int STAGE = sc.stage;
+    DevScen *sd = G.sd;
+    const int tid = threadIdx.x;
+    unsigned int sxb = wave_max_u32(acc.sxb);
+    unsigned int syb = wave_max_u32(acc.syb);
+    const bool any_def = __any(acc.deficit > 0.f);
+    double dsum = any_def ? wave_sum_f64((double)acc.deficit) : 0.0;
+    unsigned int rub = STAGE == 3 ? wave_max_u32(acc.rub) : 0u;
     __syncthreads();  // LDS tile no longer needed
     constexpr int NW = NT / 64;
     unsigned int *ru = reinterpret_cast<unsigned int *>(lds);
@@ -552,10 +621,10 @@ __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *
         if (STAGE == 3 && mr > __hip_atomic_load(&sd->runup, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             atomicMax(&sd->runup, mr);
         if ((mx >= 0x7f800000u || my >= 0x7f800000u)) atomicOr(&sd->flags, 1u);
-        // bookkeeping done once per stage by the first tile
-        if (tx == 0 && ty == 0) {
+        // bookkeeping done once per stage
+        if (first) {
             if (STAGE == 1) {
-                sd->dt = dt;
+                sd->dt = sc.dt;
                 sd->alpha[2][0] = 0u;
                 sd->alpha[2][1] = 0u;
             } else if (STAGE == 2) {
@@ -564,11 +633,28 @@ __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *
             } else {
                 sd->alpha[1][0] = 0u;
                 sd->alpha[1][1] = 0u;
-                sd->t += (double)dt;
+                sd->t += (double)sc.dt;
                 sd->step += 1;
             }
         }
     }
+}
+
+// The whole stage on one tile (one block, one tile).
+// PF as for tile_compute.
+template <class C, bool PF>
+__device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *lds, const int STAGE)
+{
+    const StageScalars sc = stage_scalars(G, STAGE);
+    {
+        TileRegs<C> v;
+        tile_load<C>(G, STAGE, tx, ty, v);
+        tile_store<C>(G, tx, ty, v, lds);
+    }
+    __syncthreads();
+    StagePartials acc;
+    tile_compute<C, PF>(G, sc, tx, ty, lds, acc);
+    stage_publish<C>(G, sc, acc, tx == 0 && ty == 0, lds);
 }
 
 }  // namespace swe
