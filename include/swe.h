@@ -86,7 +86,8 @@ typedef struct swe_ctx swe_ctx;
  * manning_n the Manning coefficient per cell, (h0, hu0, hv0) the initial
  * state; all [ny][nx] float32, host or device.  hip_stream is a hipStream_t
  * (NULL: the library creates its own); every later call of this context is
- * ordered on it.  Errors: SWE_EINVAL for nx or ny < 3, dx or dy <= 0,
+ * ordered on it.  Errors: SWE_EINVAL for nx or ny < 3, a grid of 2^30 or
+ * more elements once rows are padded to multiples of 64, dx or dy <= 0,
  * cfl <= 0 with dt_fixed <= 0, an unknown boundary kind, or any non-finite
  * value, h0 < 0 or manning_n < 0; SWE_ENOMEM, SWE_EDEVICE otherwise.  On
  * error *out is NULL. */

@@ -169,7 +169,9 @@ int validate_params(const swe_params *p)
 {
     if (!p) return SWE_EINVAL;
     if (p->nx < 3 || p->ny < 3) return SWE_EINVAL;
-    if ((long long)p->nx * p->ny > (1ll << 31) / 4) return SWE_EINVAL;
+    // every plane (row pitch x ny) must stay below 2^30 elements: the kernels
+    // address planes with 32-bit byte offsets
+    if ((long long)plane_pitch(p->nx) * p->ny >= (1ll << 30)) return SWE_EINVAL;
     if (!(p->dx > 0.0) || !(p->dy > 0.0) || !std::isfinite(p->dx) || !std::isfinite(p->dy))
         return SWE_EINVAL;
     if (!(p->g > 0.0) || !std::isfinite(p->g)) return SWE_EINVAL;

@@ -79,6 +79,19 @@ __device__ __forceinline__ int ghost_index(const Geo &G, int side, int field, in
 
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Plane element access by a 32-bit element index.  A plane holds fewer than
+// 2^30 elements (checked at creation), so the byte offset fits 32 bits and the
+// access takes the scalar-base + 32-bit vector-offset form: one offset
+// register serves every plane, with no 64-bit address arithmetic per plane.
+__device__ __forceinline__ float pld(const float *p, unsigned i)
+{
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(p) + (size_t)(i << 2));
+}
+__device__ __forceinline__ void pst(float *p, unsigned i, float v)
+{
+    *reinterpret_cast<float *>(reinterpret_cast<char *>(p) + (size_t)(i << 2)) = v;
+}
+
 template <int TX_, int TY_, int R_>
 struct TileCfg {
     static constexpr int TX = TX_, TY = TY_, R = R_;
@@ -363,38 +376,56 @@ struct TileRegs {
     float h[IT], hu[IT], hv[IT], b[IT];
 };
 
+// A tile whose halo lies inside the grid: staged without mirroring, frozen
+// ghosts or index clamping.
+template <class C>
+__device__ __forceinline__ bool tile_inner(const Geo &G, int tx, int ty)
+{
+    const int x0 = tx * C::TX, y0 = ty * C::TY;
+    return x0 >= HALO && y0 >= HALO && x0 + C::TX + HALO <= G.nx && y0 + C::TY + HALO <= G.ny;
+}
+
 // Global loads of a tile and its halo.  Ghost cells of mirrored sides read
 // the mirror cell; indices are clamped into the grid, so the cells beyond
 // three ghost layers that only ragged tail tiles touch read finite values
 // whose results are discarded.  All loads are issued back to back.
-template <class C>
+template <class C, bool INNER>
 __device__ __forceinline__ void tile_load(const Geo &G, int STAGE, int tx, int ty, TileRegs<C> &v)
 {
     const float *const *W = STAGE == 1 ? G.U : STAGE == 2 ? G.A : G.B;
     const float *w0 = W[0], *w1 = W[1], *w2 = W[2];
     const int nx = G.nx, ny = G.ny, pitch = G.pitch;
     const int x0 = tx * C::TX, y0 = ty * C::TY;
+    constexpr int NE = TileRegs<C>::NE, IT = TileRegs<C>::IT;
 #pragma unroll
-    for (int it = 0; it < TileRegs<C>::IT; ++it) {
-        const int e = threadIdx.x + it * C::NT;
+    for (int it = 0; it < IT; ++it) {
+        // spare threads of the last round restage the tile's last cell
+        // (same value to the same LDS word), which keeps the round branch-free
+        int e = threadIdx.x + it * C::NT;
+        e = (IT * C::NT == NE || e < NE) ? e : NE - 1;
         const int r = e / C::WX;
         const int cc = e - r * C::WX;
-        const int gx = x0 - HALO + cc, gy = y0 - HALO + r;
-        int mx = gx < 0 ? -1 - gx : (gx >= nx ? 2 * nx - 1 - gx : gx);
-        int my = gy < 0 ? -1 - gy : (gy >= ny ? 2 * ny - 1 - gy : gy);
-        mx = mx < 0 ? 0 : (mx >= nx ? nx - 1 : mx);
-        my = my < 0 ? 0 : (my >= ny ? ny - 1 : my);
-        const int i = my * pitch + mx;
-        v.h[it] = w0[i];
-        v.hu[it] = w1[i];
-        v.hv[it] = w2[i];
-        v.b[it] = G.b[i];
+        unsigned i;
+        if (INNER) {
+            i = (unsigned)((y0 - HALO + r) * pitch + x0 - HALO + cc);
+        } else {
+            const int gx = x0 - HALO + cc, gy = y0 - HALO + r;
+            int mx = gx < 0 ? -1 - gx : (gx >= nx ? 2 * nx - 1 - gx : gx);
+            int my = gy < 0 ? -1 - gy : (gy >= ny ? 2 * ny - 1 - gy : gy);
+            mx = mx < 0 ? 0 : (mx >= nx ? nx - 1 : mx);
+            my = my < 0 ? 0 : (my >= ny ? ny - 1 : my);
+            i = (unsigned)(my * pitch + mx);
+        }
+        v.h[it] = pld(w0, i);
+        v.hu[it] = pld(w1, i);
+        v.hv[it] = pld(w2, i);
+        v.b[it] = pld(G.b, i);
     }
 }
 
 // LDS stores of a loaded tile: normal momentum negated on mirrored ghosts,
 // frozen values on FIXED sides.
-template <class C>
+template <class C, bool INNER>
 __device__ __forceinline__ void tile_store(const Geo &G, int tx, int ty, const TileRegs<C> &v, float *lds)
 {
     float *Lh = lds, *Lhu = lds + C::PLANE, *Lhv = lds + 2 * C::PLANE, *Lb = lds + 3 * C::PLANE;
@@ -403,10 +434,18 @@ __device__ __forceinline__ void tile_store(const Geo &G, int tx, int ty, const T
     constexpr int NE = TileRegs<C>::NE, IT = TileRegs<C>::IT;
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-        const int e = threadIdx.x + it * C::NT;
-        if (IT * C::NT != NE && e >= NE) break;
+        int e = threadIdx.x + it * C::NT;
+        e = (IT * C::NT == NE || e < NE) ? e : NE - 1;
         const int r = e / C::WX;
         const int cc = e - r * C::WX;
+        const int li = r * C::SX + cc;
+        if (INNER) {
+            Lh[li] = v.h[it];
+            Lhu[li] = v.hu[it];
+            Lhv[li] = v.hv[it];
+            Lb[li] = v.b[it];
+            continue;
+        }
         const int gx = x0 - HALO + cc, gy = y0 - HALO + r;
         const bool inx = (unsigned)gx < (unsigned)nx, iny = (unsigned)gy < (unsigned)ny;
         float h = v.h[it], hu = v.hu[it], hv = v.hv[it], b = v.b[it];
@@ -424,7 +463,6 @@ __device__ __forceinline__ void tile_store(const Geo &G, int tx, int ty, const T
                 b = G.ghost[ghost_index(G, side, 3, layer, pos)];
             }
         }
-        const int li = r * C::SX + cc;
         Lh[li] = h;
         Lhu[li] = hu;
         Lhv[li] = hv;
@@ -484,12 +522,12 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int gy = y0 + seg * R + k;
-            const int gi = (gy < ny ? gy : ny - 1) * pitch + cx;
-            pgn2[k] = G.gn2[gi];
+            const unsigned gi = (unsigned)((gy < ny ? gy : ny - 1) * pitch + cx);
+            pgn2[k] = pld(G.gn2, gi);
             if (STAGE != 1) {
-                pun[k][0] = G.U[0][gi];
-                pun[k][1] = G.U[1][gi];
-                pun[k][2] = G.U[2][gi];
+                pun[k][0] = pld(G.U[0], gi);
+                pun[k][1] = pld(G.U[1], gi);
+                pun[k][2] = pld(G.U[2], gi);
             }
         }
     }
@@ -509,7 +547,7 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
         const int ly = seg * R + k;
         const int gy = y0 + ly;
         if (gx >= nx || gy >= ny) continue;
-        const int gi = gy * pitch + gx;
+        const unsigned gi = (unsigned)(gy * pitch + gx);
         const int li = (ly + HALO) * C::SX + col + HALO;
         const int xi = ly * C::XR + col;
         const float h = Lh[li], hu = Lhu[li], hv = Lhv[li];
@@ -517,7 +555,7 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
         float Lhu_ = Xr[C::XPLANE + xi] + res[k][1];
         float Lhv_ = Xr[2 * C::XPLANE + xi] + res[k][2];
         // explicit Manning friction, wet cells only, rate capped at kappa_cap/dt
-        const float gn2 = PF ? pgn2[k] : G.gn2[gi];
+        const float gn2 = PF ? pgn2[k] : pld(G.gn2, gi);
         if (h > h_dry && gn2 > 0.f) {
             const float qn = sqrtf(fmaf(hu, hu, hv * hv));
             const float hm73 = __builtin_amdgcn_exp2f(-2.33333333333333f * __builtin_amdgcn_logf(h));
@@ -527,17 +565,17 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
         }
         float oh = fmaf(dt, Lh_, h), ohu = fmaf(dt, Lhu_, hu), ohv = fmaf(dt, Lhv_, hv);
         if (STAGE == 2) {
-            oh = fmaf(0.75f, PF ? pun[k][0] : G.U[0][gi], 0.25f * oh);
-            ohu = fmaf(0.75f, PF ? pun[k][1] : G.U[1][gi], 0.25f * ohu);
-            ohv = fmaf(0.75f, PF ? pun[k][2] : G.U[2][gi], 0.25f * ohv);
+            oh = fmaf(0.75f, PF ? pun[k][0] : pld(G.U[0], gi), 0.25f * oh);
+            ohu = fmaf(0.75f, PF ? pun[k][1] : pld(G.U[1], gi), 0.25f * ohu);
+            ohv = fmaf(0.75f, PF ? pun[k][2] : pld(G.U[2], gi), 0.25f * ohv);
         }
         if (STAGE == 3) {
             // u^n + (2/3)(w + dt L - u^n): the FP32 weights 1/3 and 2/3 sum
             // to 1 + 3e-8, which would create mass every step; this form
             // keeps the two weights summing to exactly one
-            const float un0 = PF ? pun[k][0] : G.U[0][gi];
-            const float un1 = PF ? pun[k][1] : G.U[1][gi];
-            const float un2 = PF ? pun[k][2] : G.U[2][gi];
+            const float un0 = PF ? pun[k][0] : pld(G.U[0], gi);
+            const float un1 = PF ? pun[k][1] : pld(G.U[1], gi);
+            const float un2 = PF ? pun[k][2] : pld(G.U[2], gi);
             oh = fmaf(2.f / 3.f, oh - un0, un0);
             ohu = fmaf(2.f / 3.f, ohu - un1, un1);
             ohv = fmaf(2.f / 3.f, ohv - un2, un2);
@@ -551,9 +589,9 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
             ohu = 0.f;
             ohv = 0.f;
         }
-        O[0][gi] = oh;
-        O[1][gi] = ohu;
-        O[2][gi] = ohv;
+        pst(O[0], gi, oh);
+        pst(O[1], gi, ohu);
+        pst(O[2], gi, ohv);
         // wave speeds of the output (the next stage's input)
         const float cel = sqrtf(G.g * oh);
         const float inv = wet ? frcp(oh) : 0.f;
@@ -646,10 +684,14 @@ template <class C, bool PF>
 __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *lds, const int STAGE)
 {
     const StageScalars sc = stage_scalars(G, STAGE);
-    {
+    if (tile_inner<C>(G, tx, ty)) {
         TileRegs<C> v;
-        tile_load<C>(G, STAGE, tx, ty, v);
-        tile_store<C>(G, tx, ty, v, lds);
+        tile_load<C, true>(G, STAGE, tx, ty, v);
+        tile_store<C, true>(G, tx, ty, v, lds);
+    } else {
+        TileRegs<C> v;
+        tile_load<C, false>(G, STAGE, tx, ty, v);
+        tile_store<C, false>(G, tx, ty, v, lds);
     }
     __syncthreads();
     StagePartials acc;
