@@ -276,7 +276,7 @@ int scenario_upload_into(void *mem, const swe_params &p, const HostFields &f, hi
     g.g = (float)p.g;
     g.half_g = (float)(0.5 * p.g);
     g.h_dry = (float)p.h_dry;
-    g.eps12 = (float)(12.0 * p.weno_eps);
+    g.eps16 = (float)(16.0 * p.weno_eps);
     g.kappa_cap = (float)p.kappa_cap;
     g.cfl = (float)p.cfl;
     g.dt_fixed = (float)p.dt_fixed;

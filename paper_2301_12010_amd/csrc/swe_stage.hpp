@@ -57,7 +57,7 @@ struct Geo {
     int nx, ny, pitch;       // pitch: row stride of every plane (elements)
     int bc[4];               // west, east, south, north
     float dx, dy, inv_dx, inv_dy;
-    float g, half_g, h_dry, eps12;  // eps12 = 12 * weno_eps (indicators are kept x12)
+    float g, half_g, h_dry, eps16;  // eps16 = 16 * weno_eps (the kernels' indicator scale)
     float kappa_cap, cfl, dt_fixed;
     int pad;
     const float *b, *gn2;    // bed and g n^2 planes
@@ -109,12 +109,20 @@ struct TileCfg {
 
 // Sweep constants shared by the x and y sweeps.
 struct SweepK {
-    float ha;       // alpha / 2 of the sweep direction
-    float inv_ds;   // 1/dx or 1/dy
+    float a;        // alpha of the sweep direction
+    float hinv_ds;  // 1/(2 dx) or 1/(2 dy)
+    float ghinv_ds; // -g/(2 dx) or -g/(2 dy)
     float g, half_g, h_dry;
-    float e0, e1, e2;  // 12 eps / sqrt(d_k)
+    float e0, e1, e2;  // 16 eps / sqrt(d_k)
 };
 
+// Scales.  The sweeps reconstruct the doubled split fluxes F +- alpha u~
+// (twice the split fluxes); the halving is folded into the final difference.
+// A centre's smoothness indicators are carried as (13/3) D^2 + s^2 of the
+// doubled values, i.e. 16 beta, so epsilon enters as 16 eps.  Scaling all
+// three indicators and epsilon by one factor scales the unnormalised weights
+// by one factor, which the normalisation removes.
+//
 // WENO5 linear weights d = (1/10, 6/10, 3/10) enter as 1/sqrt(d_k): the
 // unnormalised weight d_k / (eps + beta_k)^2 is computed as 1/t^2 with
 // t = (eps + beta_k) / sqrt(d_k).
@@ -141,12 +149,14 @@ __device__ __forceinline__ void sweep(const float *__restrict__ Lh, const float 
 {
     constexpr int NF = R + 1;                 // faces k-1/2 for k = 0..R
     constexpr int MB = DIR == 0 ? 1 : 2;      // component whose weights reconstruct b
+    // accumulators start at -0, the additive identity the compiler may fold
+    // away (x + -0 == x for every x), so a first contribution costs no add
     float np_[NF][3], dp_[NF][3], nm_[NF][3], dm_[NF][3], nbp[NF], nbm[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
 #pragma unroll
-        for (int m = 0; m < 3; ++m) np_[f][m] = dp_[f][m] = nm_[f][m] = dm_[f][m] = 0.f;
-        nbp[f] = nbm[f] = 0.f;
+        for (int m = 0; m < 3; ++m) np_[f][m] = dp_[f][m] = nm_[f][m] = dm_[f][m] = -0.f;
+        nbp[f] = nbm[f] = -0.f;
     }
     float win[3][7];   // rolling window: F+ (3), F- (3), b
 #pragma unroll
@@ -179,12 +189,12 @@ __device__ __forceinline__ void sweep(const float *__restrict__ Lh, const float 
             win[0][q] = win[1][q];
             win[1][q] = win[2][q];
         }
-        win[2][0] = fmaf(K.ha, e, 0.5f * F0);
-        win[2][1] = fmaf(K.ha, hu, 0.5f * F1);
-        win[2][2] = fmaf(K.ha, hv, 0.5f * F2);
-        win[2][3] = fmaf(-K.ha, e, 0.5f * F0);
-        win[2][4] = fmaf(-K.ha, hu, 0.5f * F1);
-        win[2][5] = fmaf(-K.ha, hv, 0.5f * F2);
+        win[2][0] = fmaf(K.a, e, F0);
+        win[2][1] = fmaf(K.a, hu, F1);
+        win[2][2] = fmaf(K.a, hv, F2);
+        win[2][3] = fmaf(-K.a, e, F0);
+        win[2][4] = fmaf(-K.a, hu, F1);
+        win[2][5] = fmaf(-K.a, hv, F2);
         win[2][6] = b;
         if (w >= 0 && w < R) eta[w >= 0 && w < R ? w : 0] = e;
         if (w < -1) continue;
@@ -207,12 +217,12 @@ __device__ __forceinline__ void sweep(const float *__restrict__ Lh, const float 
             const float vm = win[0][q], v0 = win[1][q], vp = win[2][q];
             const float D = fmaf(-2.f, v0, vm + vp);
             const float E = vp - vm;
-            const float base = (13.f * D) * D;
+            const float base = ((13.f / 3.f) * D) * D;
             const float sR = fmaf(2.f, D, E);
             const float sL = fmaf(2.f, D, -E);
-            const float bM_ = fmaf(3.f * E, E, base);     // 12 x indicator, centred stencil
-            const float bR_ = fmaf(3.f * sR, sR, base);   // stencil whose right end is the face side
-            const float bL_ = fmaf(3.f * sL, sL, base);
+            const float bM_ = fmaf(E, E, base);     // 16 x indicator, centred stencil
+            const float bR_ = fmaf(sR, sR, base);   // stencil whose right end is the face side
+            const float bL_ = fmaf(sL, sL, base);
             const float t0 = fmaf(D, 1.f / 12.f, v0);
             const float pR = fmaf(E, 0.25f, t0);          // value at c + 1/2
             const float pL = fmaf(E, -0.25f, t0);         // value at c - 1/2
@@ -282,13 +292,14 @@ __device__ __forceinline__ void sweep(const float *__restrict__ Lh, const float 
                     rm_b = rm;
                 }
             }
-            const float bh = 0.5f * fmaf(nbp[f], rp_b, nbm[f] * rm_b);
+            // twice the face value of b (mean of the two reconstructions)
+            const float bh = fmaf(nbp[f], rp_b, nbm[f] * rm_b);
             if (f >= 1) {
                 const int k = f - 1;
                 float r3[3];
 #pragma unroll
-                for (int m = 0; m < 3; ++m) r3[m] = (fprev[m] - Fh[m]) * K.inv_ds;
-                r3[MB] = fmaf(-K.g * eta[k], (bh - bprev) * K.inv_ds, r3[MB]);
+                for (int m = 0; m < 3; ++m) r3[m] = (fprev[m] - Fh[m]) * K.hinv_ds;
+                r3[MB] = fmaf(eta[k], (bh - bprev) * K.ghinv_ds, r3[MB]);
                 emit(k, r3[0], r3[1], r3[2]);
             }
 #pragma unroll
@@ -491,15 +502,16 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
     K.g = G.g;
     K.half_g = G.half_g;
     K.h_dry = G.h_dry;
-    K.e0 = G.eps12 * KD0;
-    K.e1 = G.eps12 * KD1;
-    K.e2 = G.eps12 * KD2;
+    K.e0 = G.eps16 * KD0;
+    K.e1 = G.eps16 * KD1;
+    K.e2 = G.eps16 * KD2;
 
     // ---- x sweep: thread -> (row, segment of R cells) ------------------------
     {
         const int row = tid % TY, seg = tid / TY;
-        K.ha = 0.5f * sc.ax;
-        K.inv_ds = G.inv_dx;
+        K.a = sc.ax;
+        K.hinv_ds = 0.5f * G.inv_dx;
+        K.ghinv_ds = -G.g * K.hinv_ds;
         float *xo = Xr + row * C::XR + seg * R;
         sweep<R, 0>(Lh, Lhu, Lhv, Lb, (row + HALO) * C::SX + seg * R, 1, K,
                     [&](int k, float l0, float l1, float l2) {
@@ -532,8 +544,9 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
         }
     }
     float res[R][3];
-    K.ha = 0.5f * sc.ay;
-    K.inv_ds = G.inv_dy;
+    K.a = sc.ay;
+    K.hinv_ds = 0.5f * G.inv_dy;
+    K.ghinv_ds = -G.g * K.hinv_ds;
     sweep<R, 1>(Lh, Lhu, Lhv, Lb, (seg * R) * C::SX + col + HALO, C::SX, K,
                 [&](int k, float l0, float l1, float l2) {
                     res[k][0] = l0;
