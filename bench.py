@@ -11,6 +11,9 @@ Extra objects on the same JSON line:
   roofline      stage kernel: algorithmic flops (and bytes) per launch over
                 its mean device duration, HIP events on the kernels' stream;
   cpu_baseline  the FP64 reference checker on a bounded sample;
+  outputs       the same grid with six snapshots at output times streamed to
+                the host and the maximum-depth map kept: cost per step and
+                how long after the run the last snapshot is on the host;
   batched       the mitigation ensemble (64 x 1024^2, dx 2 m, 3000 steps,
                 seeded hills and Manning patches) in one batch: scenarios/hour
                 batched vs the plain single-scenario solver, runup;
@@ -137,8 +140,68 @@ def run_large(args, torch, inputs, swe):
                 "bytes_per_cell_launch": sum(BYTES_STAGE) / 3.0}
     roofline = roof_alu if roof_alu["frac"] >= roof_hbm["frac"] else roof_hbm
     other = roof_hbm if roofline is roof_alu else roof_alu
+    outputs = None if args.no_outputs else measure_outputs(s, torch, stream, sc)
     s.close()
-    return sc, value, ms, roofline, other, tv
+    return sc, value, ms, roofline, other, tv, outputs
+
+
+def measure_outputs(s, torch, stream, sc, steps=300, chunk=25, n_out=6):
+    """Snapshots at output times plus the maximum-depth map during a run.
+
+    The host drives the run in chunks of `chunk` steps and keeps at most two
+    chunks ahead of the GPU, polling the outputs between chunks, as a caller
+    streaming results would.  The same loop without outputs is the
+    reference.  Reports the per-step cost of the outputs and how long after
+    the last step the last snapshot reaches the host.
+    """
+    import time as _t
+
+    def run(with_outputs):
+        if with_outputs:
+            st = s.stats()
+            # about every steps / n_out steps, between step ends
+            times = [st["t"] + (j * steps / n_out - 0.5) * st["dt"] for j in range(1, n_out + 1)]
+            s.set_outputs(times)
+            s.track_max_depth(True)
+        torch.cuda.synchronize()
+        evs = []
+        ready = [False] * (n_out if with_outputs else 0)
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for i in range(steps // chunk):
+            s.step(chunk)
+            e = torch.cuda.Event()
+            e.record(stream)
+            evs.append(e)
+            if i >= 2:
+                evs[i - 2].synchronize()
+            for k in range(len(ready)):
+                ready[k] = ready[k] or s.output_ready(k)
+        stop.record(stream)
+        stop.synchronize()
+        t_end = _t.perf_counter()
+        ms = start.elapsed_time(stop)
+        on_host_early = sum(ready)
+        for k in range(len(ready)):
+            ready[k] = ready[k] or s.output_ready(k, wait=True)
+        drain_ms = (_t.perf_counter() - t_end) * 1e3
+        if with_outputs:
+            for k in range(n_out):  # hand-out into caller arrays (not timed)
+                assert s.output(k) is not None
+            s.max_depth()
+            s.set_outputs([])
+            s.track_max_depth(False)
+        return ms / steps, sum(ready), on_host_early, drain_ms
+
+    base, _, _, _ = run(False)
+    with_o, taken, early, drain = run(True)
+    res = {"steps": steps, "chunk_steps": chunk, "snapshots": taken,
+           "snapshots_on_host_before_run_end": early, "snapshot_mb": 12 * sc.cells / 1e6,
+           "max_depth_map": True, "ms_per_step": with_o, "ms_per_step_without": base,
+           "overhead": with_o / base - 1.0, "last_snapshot_ms_after_run_end": drain}
+    log(f"outputs: {res}")
+    return res
 
 
 def run_batched(args, torch, inputs, swe):
@@ -321,6 +384,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true", help="skip the ensemble and serving runs")
+    ap.add_argument("--no-outputs", action="store_true", help="skip the snapshot/max-depth measurement")
     ap.add_argument("--ens-count", type=int, default=64)
     ap.add_argument("--ens-steps", type=int, default=3000)
     ap.add_argument("--serve-requests", type=int, default=48)
@@ -350,7 +414,7 @@ def main():
     if args.workload == "serving":
         print(json.dumps(run_serving_scale(args, torch, inputs, swe)), flush=True)
         return
-    sc, value, ms, roofline, other, tv = run_large(args, torch, inputs, swe)
+    sc, value, ms, roofline, other, tv, outputs = run_large(args, torch, inputs, swe)
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
@@ -361,6 +425,8 @@ def main():
                    "tile": [tv["tx"], tv["ty"], tv["r"]], "graph_steps": args.graph_steps},
         "roofline": roofline, "roofline_other": other,
     }
+    if outputs is not None:
+        out["outputs"] = outputs
     if not args.no_batched:
         batched, members = run_batched(args, torch, inputs, swe)
         out["batched"] = batched

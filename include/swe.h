@@ -123,6 +123,44 @@ int swe_state_device(swe_ctx *ctx, float **h, float **hu, float **hv, int64_t *p
  * device duration of the stage-1, -2 and -3 launches.  Blocks until done. */
 int swe_time_stages(swe_ctx *ctx, int32_t nsteps, double *ms);
 
+/* ---- outputs during a run ------------------------------------------------
+ * The paper's runs write the state at chosen output times while the solver
+ * advances (Section 3, host orchestration of the replicated computation);
+ * here snapshots are taken on the device and streamed to the host on a copy
+ * stream, and a maximum-depth (inundation) map is kept on the device. */
+
+/* Request snapshots at n output times (simulated seconds, finite,
+ * non-decreasing).  Output k is the state at the end of the first step,
+ * enqueued after this call, whose time t >= times[k]; a step that passes
+ * several output times serves all of them.  A snapshot is copied on the
+ * device when taken and then copied to library-owned pinned host memory on
+ * a copy stream while later steps run (the transfer is enqueued by the next
+ * swe_step or swe_output_get call after the snapshot's step has finished).
+ * Memory: 12 bytes per cell and output, on the device and on the host.
+ * Replaces any previous request; n = 0 clears.  Errors: SWE_EINVAL for
+ * n < 0 or n > 65536, times NULL with n > 0, non-finite or decreasing times;
+ * SWE_ENOMEM. */
+int swe_set_outputs(swe_ctx *ctx, const double *times, int32_t n);
+
+/* Output k (0 <= k < n of the last swe_set_outputs).  Returns 1 after
+ * copying it into the caller's [ny][nx] arrays (any of h, hu, hv, t, step
+ * may be NULL); 0 if it is not available: with wait = 0, not yet on the
+ * host; with wait != 0, the steps enqueued so far do not reach times[k]
+ * (the call first waits for them and for the transfer).  SWE_EINVAL for k
+ * out of range. */
+int swe_output_get(swe_ctx *ctx, int32_t k, int32_t wait, float *h, float *hu, float *hv,
+                   double *t, int64_t *step);
+
+/* Maximum-depth map: with enable != 0, keep for every cell the maximum of h
+ * over the state at the call and the state after every later step (updated
+ * inside the last RK stage's store); enable = 0 drops the map.  Enabling
+ * again restarts it.  SWE_ENOMEM if the plane cannot be allocated. */
+int swe_track_max_depth(swe_ctx *ctx, int32_t enable);
+
+/* Wait for the context's stream, then copy the maximum-depth map ([ny][nx]).
+ * SWE_EINVAL if the map is not being kept or hmax is NULL. */
+int swe_read_max_depth(swe_ctx *ctx, float *hmax);
+
 /* ---- tile variants and autotuning --------------------------------------- */
 /* Tile variants of the stage kernel: tile width tx, height ty, cells per
  * thread along a sweep r, threads per block. Results are bitwise identical

@@ -159,6 +159,34 @@ class Oracle:
         dt = self._L.oracle_stage1(self._ptr, *[_dp(a) for a in out])
         return tuple(out), float(dt)
 
+    def run_with_outputs(self, nsteps: int, times=(), max_depth: bool = False):
+        """Advance nsteps steps one at a time, taking the run's outputs.
+
+        The paper's runs write the state at chosen output times (Section 3,
+        host orchestration).  Output k is the state at the end of the first
+        step whose time reaches times[k] (times non-decreasing); one step may
+        serve several outputs.  The maximum-depth map is, per cell, the
+        maximum of h over the starting state and the state after every step.
+        Returns (outputs, hmax): outputs[k] = (h, hu, hv, t, step) or None if
+        the run does not reach times[k]; hmax is None unless max_depth.
+        """
+        times = [float(x) for x in times]
+        outs = [None] * len(times)
+        hmax = self.state()[0].copy() if max_depth else None
+        k = 0
+        for _ in range(int(nsteps)):
+            rc = self.step(1)
+            if rc != 0:
+                raise RuntimeError(f"oracle step failed ({rc})")
+            h, hu, hv = self.state()
+            if max_depth:
+                np.maximum(hmax, h, out=hmax)
+            sc = self.scalars()
+            while k < len(times) and sc["t"] >= times[k]:
+                outs[k] = (h, hu, hv, sc["t"], sc["step"])
+                k += 1
+        return outs, hmax
+
     def close(self):
         if getattr(self, "_ptr", None):
             self._L.oracle_destroy(self._ptr)

@@ -3,6 +3,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -115,6 +116,76 @@ int launch_mass(const Geo &g, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_mass_part, dim3(MASS_BLOCKS), dim3(256), 0, stream, g);
     hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(64), 0, stream, g);
+    return hipGetLastError() == hipSuccess ? SWE_OK : SWE_EDEVICE;
+}
+
+// ---------------------------------------------------------------------------
+// outputs during a run: snapshots at output times, maximum-depth map
+// ---------------------------------------------------------------------------
+// Device bookkeeping of an output request: `next` is the first output not yet
+// taken; hdr[k] describes output k once taken (src: the output whose slot
+// holds the state, when one step served several output times).
+struct SnapHeader {
+    double t;
+    long long step;
+    int src;
+    int pad[3];
+};
+struct SnapMeta {
+    int next, n;
+    int pad[6];
+    SnapHeader hdr[1];  // n entries
+};
+
+static size_t snap_meta_bytes(int n) { return offsetof(SnapMeta, hdr) + (size_t)n * sizeof(SnapHeader); }
+
+// Copy u^n into output slot `next` if the step just completed reached its
+// time.  Every block takes the same decision: nothing writes `next` or t in
+// this kernel.  Planes are copied whole (pitch included), four floats per
+// access (the pitch is a multiple of 64).
+__global__ __launch_bounds__(256) void k_snap_copy(Geo G, const double *times, const SnapMeta *m,
+                                                   float *slots)
+{
+    const int j = m->next;
+    if (j >= m->n || !(G.sd->t >= times[j])) return;
+    const size_t plane = (size_t)G.pitch * G.ny;
+    const size_t q = plane / 4;
+    float4 *dst = reinterpret_cast<float4 *>(slots + (size_t)j * 3 * plane);
+    const float4 *s0 = reinterpret_cast<const float4 *>(G.U[0]);
+    const float4 *s1 = reinterpret_cast<const float4 *>(G.U[1]);
+    const float4 *s2 = reinterpret_cast<const float4 *>(G.U[2]);
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < q; i += (size_t)gridDim.x * 256) {
+        dst[i] = s0[i];
+        dst[q + i] = s1[i];
+        dst[2 * q + i] = s2[i];
+    }
+}
+
+// Advance `next` past every output time the step reached (one thread).
+__global__ __launch_bounds__(64) void k_snap_advance(Geo G, const double *times, SnapMeta *m)
+{
+    if (threadIdx.x != 0) return;
+    int j = m->next;
+    const double t = G.sd->t;
+    if (j >= m->n || !(t >= times[j])) return;
+    const int src = j;
+    const long long step = G.sd->step;
+    while (j < m->n && t >= times[j]) {
+        m->hdr[j].t = t;
+        m->hdr[j].step = step;
+        m->hdr[j].src = src;
+        ++j;
+    }
+    m->next = j;
+}
+
+static int launch_snap(const Geo &g, const double *times, SnapMeta *m, float *slots, hipStream_t stream)
+{
+    const size_t q = (size_t)g.pitch * g.ny / 4;
+    size_t blocks = (q + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_snap_copy, dim3((unsigned)blocks), dim3(256), 0, stream, g, times, m, slots);
+    hipLaunchKernelGGL(k_snap_advance, dim3(1), dim3(64), 0, stream, g, times, m);
     return hipGetLastError() == hipSuccess ? SWE_OK : SWE_EDEVICE;
 }
 
@@ -294,6 +365,7 @@ int scenario_upload_into(void *mem, const swe_params &p, const HostFields &f, hi
     const size_t ghost_b = align256(((size_t)24 * ny + (size_t)24 * nx) * sizeof(float));
     g.sd = reinterpret_cast<DevScen *>(base + 11 * plane + ghost_b);
     g.mass_part = reinterpret_cast<double *>(base + 11 * plane + ghost_b + align256(sizeof(DevScen)));
+    g.hmax = nullptr;
 
     const size_t N = (size_t)nx * ny;
     std::vector<float> gn2(N);
@@ -387,6 +459,27 @@ int scenario_read(const DevScenario &d, hipStream_t stream, float *h, float *hu,
 // ---------------------------------------------------------------------------
 using namespace swe;
 
+// Output request of a context (swe_set_outputs).  Snapshot slots and headers
+// live on the device; `meta` is copied to one of two pinned buffers after
+// every swe_step (double-buffered, each with an event), and once a copy has
+// landed the host enqueues the transfers of newly taken snapshots on the
+// copy stream behind that event.
+struct OutputSet {
+    int n = 0;
+    double *d_times = nullptr;
+    SnapMeta *d_meta = nullptr;
+    float *d_slots = nullptr;  // n x 3 planes (pitch x ny)
+    float *h_data = nullptr;   // pinned, n x 3 x ny x nx
+    SnapMeta *h_meta[2] = {nullptr, nullptr};
+    hipEvent_t ev_meta[2] = {nullptr, nullptr};
+    bool meta_pending[2] = {false, false};
+    int meta_turn = 0;
+    int known = 0;                 // outputs known to be taken
+    std::vector<SnapHeader> hdr;   // headers of taken outputs
+    std::vector<hipEvent_t> ev_copy;
+    std::vector<char> queued;
+};
+
 struct swe_ctx {
     swe_params p{};
     DevScenario d;
@@ -398,6 +491,9 @@ struct swe_ctx {
     hipGraphExec_t graph = nullptr;
     int graph_k = 0;
     int graph_tile = -1;
+    OutputSet out;
+    hipStream_t copy_stream = nullptr;
+    float *d_hmax = nullptr;
 };
 
 static int ctx_tile(const swe_ctx *c)
@@ -408,11 +504,100 @@ static int ctx_tile(const swe_ctx *c)
 static int enqueue_steps(swe_ctx *c, int n)
 {
     const Variant &v = variant(ctx_tile(c));
-    for (int s = 0; s < n; ++s)
+    for (int s = 0; s < n; ++s) {
         for (int st = 1; st <= 3; ++st) {
             const int rc = launch_stage(v, st, c->d.geo, c->stream);
             if (rc) return rc;
         }
+        if (c->out.n > 0) {
+            const int rc = launch_snap(c->d.geo, c->out.d_times, c->out.d_meta, c->out.d_slots, c->stream);
+            if (rc) return rc;
+        }
+    }
+    return SWE_OK;
+}
+
+// ---- outputs ----------------------------------------------------------------
+
+static void outputs_free(swe_ctx *c)
+{
+    OutputSet &o = c->out;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->copy_stream) (void)hipStreamSynchronize(c->copy_stream);
+    for (hipEvent_t e : o.ev_copy)
+        if (e) (void)hipEventDestroy(e);
+    for (int b = 0; b < 2; ++b) {
+        if (o.ev_meta[b]) (void)hipEventDestroy(o.ev_meta[b]);
+        if (o.h_meta[b]) (void)hipHostFree(o.h_meta[b]);
+    }
+    if (o.h_data) (void)hipHostFree(o.h_data);
+    if (o.d_slots) (void)hipFree(o.d_slots);
+    if (o.d_meta) (void)hipFree(o.d_meta);
+    if (o.d_times) (void)hipFree(o.d_times);
+    o = OutputSet();
+}
+
+// Enqueue the host transfer of output k (its state sits in slot hdr[k].src)
+// on the copy stream, behind the event of the metadata copy that reported it.
+static int outputs_queue_copy(swe_ctx *c, int k, hipEvent_t after)
+{
+    OutputSet &o = c->out;
+    const Geo &g = c->d.geo;
+    const size_t plane = (size_t)g.pitch * g.ny;
+    const size_t cells = (size_t)g.nx * g.ny;
+    const size_t row = (size_t)g.nx * sizeof(float), spitch = (size_t)g.pitch * sizeof(float);
+    const int src = o.hdr[k].src;
+    SWE_HIP_TRY(hipStreamWaitEvent(c->copy_stream, after, 0));
+    for (int f = 0; f < 3; ++f)
+        SWE_HIP_TRY(hipMemcpy2DAsync(o.h_data + ((size_t)k * 3 + f) * cells, row,
+                                     o.d_slots + ((size_t)src * 3 + f) * plane, spitch, row, g.ny,
+                                     hipMemcpyDeviceToHost, c->copy_stream));
+    SWE_HIP_TRY(hipEventRecord(o.ev_copy[k], c->copy_stream));
+    o.queued[k] = 1;
+    return SWE_OK;
+}
+
+// Take in the metadata copies that have landed (waiting for them if block)
+// and queue the transfers of outputs they report as taken.
+static int outputs_service(swe_ctx *c, bool block)
+{
+    OutputSet &o = c->out;
+    for (int i = 0; i < 2; ++i) {
+        const int b = (o.meta_turn + i) & 1;  // older copy first
+        if (!o.meta_pending[b]) continue;
+        const hipError_t e = block ? hipEventSynchronize(o.ev_meta[b]) : hipEventQuery(o.ev_meta[b]);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) return SWE_EDEVICE;
+        o.meta_pending[b] = false;
+        const SnapMeta *m = o.h_meta[b];
+        const int next = m->next < o.n ? m->next : o.n;
+        for (int k = o.known; k < next; ++k) {
+            o.hdr[k] = m->hdr[k];
+            if (o.hdr[k].src < 0 || o.hdr[k].src > k) return SWE_EDEVICE;
+            const int rc = outputs_queue_copy(c, k, o.ev_meta[b]);
+            if (rc) return rc;
+        }
+        if (next > o.known) o.known = next;
+    }
+    return SWE_OK;
+}
+
+// After new steps: copy the metadata to a free pinned buffer.
+static int outputs_post(swe_ctx *c)
+{
+    OutputSet &o = c->out;
+    if (o.n == 0) return SWE_OK;
+    int rc = outputs_service(c, false);
+    if (rc) return rc;
+    int b = o.meta_turn;
+    if (o.meta_pending[b]) {
+        b ^= 1;
+        if (o.meta_pending[b]) return SWE_OK;  // both in flight: the next call posts
+    }
+    SWE_HIP_TRY(hipMemcpyAsync(o.h_meta[b], o.d_meta, snap_meta_bytes(o.n), hipMemcpyDeviceToHost, c->stream));
+    SWE_HIP_TRY(hipEventRecord(o.ev_meta[b], c->stream));
+    o.meta_pending[b] = true;
+    o.meta_turn = b ^ 1;
     return SWE_OK;
 }
 
@@ -491,7 +676,9 @@ int swe_step(swe_ctx *c, int32_t nsteps)
             n -= c->graph_k;
         }
     }
-    return enqueue_steps(c, n);
+    const int rc = enqueue_steps(c, n);
+    if (rc) return rc;
+    return nsteps > 0 ? outputs_post(c) : SWE_OK;
 }
 
 int swe_read(swe_ctx *c, float *h, float *hu, float *hv, swe_stats *st)
@@ -505,9 +692,139 @@ void swe_destroy(swe_ctx *c)
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graph(c);
+    outputs_free(c);
+    if (c->d_hmax) (void)hipFree(c->d_hmax);
+    if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
     scenario_free(c->d);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
+}
+
+int swe_set_outputs(swe_ctx *c, const double *times, int32_t n)
+{
+    if (!c || n < 0 || n > 65536 || (n > 0 && !times)) return SWE_EINVAL;
+    for (int k = 0; k < n; ++k)
+        if (!std::isfinite(times[k]) || (k > 0 && times[k] < times[k - 1])) return SWE_EINVAL;
+    drop_graph(c);  // captured steps refer to the old request
+    outputs_free(c);
+    if (n == 0) return SWE_OK;
+    OutputSet &o = c->out;
+    const Geo &g = c->d.geo;
+    const size_t plane = (size_t)g.pitch * g.ny, cells = (size_t)g.nx * g.ny;
+    int rc = SWE_ENOMEM;
+    if (!c->copy_stream && hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+        c->copy_stream = nullptr;
+        return SWE_EDEVICE;
+    }
+    o.n = n;
+    o.hdr.assign(n, SnapHeader{});
+    o.ev_copy.assign(n, nullptr);
+    o.queued.assign(n, 0);
+    if (hipMalloc(&o.d_times, n * sizeof(double)) != hipSuccess ||
+        hipMalloc(&o.d_meta, snap_meta_bytes(n)) != hipSuccess ||
+        hipMalloc(&o.d_slots, (size_t)n * 3 * plane * sizeof(float)) != hipSuccess ||
+        hipHostMalloc(&o.h_data, (size_t)n * 3 * cells * sizeof(float), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&o.h_meta[0], snap_meta_bytes(n), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&o.h_meta[1], snap_meta_bytes(n), hipHostMallocDefault) != hipSuccess)
+        goto fail;
+    rc = SWE_EDEVICE;
+    for (int b = 0; b < 2; ++b)
+        if (hipEventCreateWithFlags(&o.ev_meta[b], hipEventDisableTiming) != hipSuccess) goto fail;
+    for (int k = 0; k < n; ++k)
+        if (hipEventCreateWithFlags(&o.ev_copy[k], hipEventDisableTiming) != hipSuccess) goto fail;
+    {
+        std::vector<char> meta(snap_meta_bytes(n), 0);
+        SnapMeta *m = reinterpret_cast<SnapMeta *>(meta.data());
+        m->next = 0;
+        m->n = n;
+        if (hipMemcpyAsync(o.d_times, times, n * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(o.d_meta, meta.data(), meta.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            goto fail;
+    }
+    return SWE_OK;
+fail:
+    (void)hipGetLastError();
+    outputs_free(c);
+    return rc;
+}
+
+int swe_output_get(swe_ctx *c, int32_t k, int32_t wait, float *h, float *hu, float *hv, double *t,
+                   int64_t *step)
+{
+    if (!c || k < 0 || k >= c->out.n) return SWE_EINVAL;
+    OutputSet &o = c->out;
+    int rc = outputs_service(c, false);
+    if (rc) return rc;
+    if (!o.queued[k] && wait) {
+        // everything enqueued so far: wait for it and read the metadata
+        SWE_HIP_TRY(hipStreamSynchronize(c->stream));
+        rc = outputs_service(c, true);
+        if (rc) return rc;
+        if (!o.queued[k]) {
+            SWE_HIP_TRY(hipMemcpyAsync(o.h_meta[0], o.d_meta, snap_meta_bytes(o.n), hipMemcpyDeviceToHost,
+                                       c->stream));
+            SWE_HIP_TRY(hipStreamSynchronize(c->stream));
+            const SnapMeta *m = o.h_meta[0];
+            const int next = m->next < o.n ? m->next : o.n;
+            if (next > o.known) {
+                SWE_HIP_TRY(hipEventRecord(o.ev_meta[0], c->stream));
+                for (int j = o.known; j < next; ++j) {
+                    o.hdr[j] = m->hdr[j];
+                    if (o.hdr[j].src < 0 || o.hdr[j].src > j) return SWE_EDEVICE;
+                    rc = outputs_queue_copy(c, j, o.ev_meta[0]);
+                    if (rc) return rc;
+                }
+                o.known = next;
+            }
+        }
+    }
+    if (!o.queued[k]) return 0;
+    const hipError_t e = wait ? hipEventSynchronize(o.ev_copy[k]) : hipEventQuery(o.ev_copy[k]);
+    if (e == hipErrorNotReady) return 0;
+    if (e != hipSuccess) return SWE_EDEVICE;
+    const Geo &g = c->d.geo;
+    const size_t cells = (size_t)g.nx * g.ny;
+    float *outs[3] = {h, hu, hv};
+    for (int f = 0; f < 3; ++f)
+        if (outs[f]) std::memcpy(outs[f], o.h_data + ((size_t)k * 3 + f) * cells, cells * sizeof(float));
+    if (t) *t = o.hdr[k].t;
+    if (step) *step = o.hdr[k].step;
+    return 1;
+}
+
+int swe_track_max_depth(swe_ctx *c, int32_t enable)
+{
+    if (!c) return SWE_EINVAL;
+    drop_graph(c);  // captured steps carry the plane's address
+    if (c->d_hmax) {
+        SWE_HIP_TRY(hipStreamSynchronize(c->stream));
+        (void)hipFree(c->d_hmax);
+        c->d_hmax = nullptr;
+        c->d.geo.hmax = nullptr;
+    }
+    if (!enable) return SWE_OK;
+    const Geo &g = c->d.geo;
+    const size_t bytes = (size_t)g.pitch * g.ny * sizeof(float);
+    if (hipMalloc(&c->d_hmax, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        c->d_hmax = nullptr;
+        return SWE_ENOMEM;
+    }
+    // start from the current depth, after the work already enqueued
+    SWE_HIP_TRY(hipMemcpyAsync(c->d_hmax, g.U[0], bytes, hipMemcpyDeviceToDevice, c->stream));
+    c->d.geo.hmax = c->d_hmax;
+    return SWE_OK;
+}
+
+int swe_read_max_depth(swe_ctx *c, float *hmax)
+{
+    if (!c || !hmax || !c->d_hmax) return SWE_EINVAL;
+    const Geo &g = c->d.geo;
+    const size_t row = (size_t)g.nx * sizeof(float), spitch = (size_t)g.pitch * sizeof(float);
+    SWE_HIP_TRY(hipMemcpy2DAsync(hmax, row, c->d_hmax, spitch, row, g.ny, hipMemcpyDeviceToHost, c->stream));
+    SWE_HIP_TRY(hipStreamSynchronize(c->stream));
+    return SWE_OK;
 }
 
 int swe_set_option(swe_ctx *c, int32_t key, int64_t value)

@@ -65,6 +65,7 @@ struct Geo {
     const float *ghost;      // frozen FIXED ghosts, see ghost_index()
     DevScen *sd;
     double *mass_part;       // MASS_BLOCKS partial sums of the mass kernel
+    float *hmax;             // maximum-depth plane (same pitch), or null
 };
 
 // Frozen ghosts of a FIXED side: [field h,hu,hv,b][layer 0..2][position along the side].
@@ -605,6 +606,10 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
         pst(O[0], gi, oh);
         pst(O[1], gi, ohu);
         pst(O[2], gi, ohv);
+        if (STAGE == 3 && G.hmax) {
+            // maximum-depth map over the states after completed steps
+            if (oh > pld(G.hmax, gi)) pst(G.hmax, gi, oh);
+        }
         // wave speeds of the output (the next stage's input)
         const float cel = sqrtf(G.g * oh);
         const float inv = wet ? frcp(oh) : 0.f;

@@ -84,6 +84,11 @@ _SIGS = {
     "swe_state_device": (ctypes.c_int, [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
                                         ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int64)]),
     "swe_time_stages": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "swe_set_outputs": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
+    "swe_output_get": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, _FP, _FP, _FP,
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "swe_track_max_depth": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "swe_read_max_depth": (ctypes.c_int, [_VP, _FP]),
     "swe_tile_info": (ctypes.c_int, [ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 4),
     "swe_tile_count": (ctypes.c_int, []),
     "swe_autotune": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p,
@@ -240,6 +245,41 @@ class Solver:
 
     def set_option(self, key: int, value: int):
         _check(_lib().swe_set_option(self._ctx, int(key), int(value)), "swe_set_option")
+
+    def set_outputs(self, times):
+        """Request snapshots at the given simulated times (see swe_set_outputs)."""
+        t = np.ascontiguousarray(times, dtype=np.float64)
+        arr = (ctypes.c_double * max(len(t), 1))(*t.tolist())
+        _check(_lib().swe_set_outputs(self._ctx, arr, len(t)), "swe_set_outputs")
+
+    def output(self, k: int, wait: bool = False):
+        """Snapshot k as (h, hu, hv, t, step), or None while it is not available."""
+        h = np.empty((self.ny, self.nx), np.float32)
+        hu = np.empty_like(h)
+        hv = np.empty_like(h)
+        t = ctypes.c_double()
+        st = ctypes.c_int64()
+        rc = _lib().swe_output_get(self._ctx, int(k), int(bool(wait)), h.ctypes.data, hu.ctypes.data,
+                                   hv.ctypes.data, ctypes.byref(t), ctypes.byref(st))
+        if rc < 0:
+            raise SweError(rc, "swe_output_get")
+        return (h, hu, hv, t.value, st.value) if rc == 1 else None
+
+    def output_ready(self, k: int, wait: bool = False) -> bool:
+        """Whether snapshot k is on the host (copies nothing; moves the
+        transfers of newly taken snapshots onto the copy stream)."""
+        rc = _lib().swe_output_get(self._ctx, int(k), int(bool(wait)), None, None, None, None, None)
+        if rc < 0:
+            raise SweError(rc, "swe_output_get")
+        return rc == 1
+
+    def track_max_depth(self, enable: bool = True):
+        _check(_lib().swe_track_max_depth(self._ctx, int(bool(enable))), "swe_track_max_depth")
+
+    def max_depth(self):
+        hm = np.empty((self.ny, self.nx), np.float32)
+        _check(_lib().swe_read_max_depth(self._ctx, hm.ctypes.data), "swe_read_max_depth")
+        return hm
 
     def close(self):
         if getattr(self, "_ctx", None):
