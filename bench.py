@@ -11,6 +11,7 @@ Extra objects on the same JSON line:
   roofline      stage kernel: algorithmic flops (and bytes) per launch over
                 its mean device duration, HIP events on the kernels' stream;
   cpu_baseline  the FP64 reference checker on a bounded sample;
+  small_grid    the 128 x 64 dam break: ms per step with graph replays;
   outputs       the same grid with six snapshots at output times streamed to
                 the host and the maximum-depth map kept: cost per step and
                 how long after the run the last snapshot is on the host;
@@ -143,6 +144,34 @@ def run_large(args, torch, inputs, swe):
     outputs = None if args.no_outputs else measure_outputs(s, torch, stream, sc)
     s.close()
     return sc, value, ms, roofline, other, tv, outputs
+
+
+def measure_small_grid(torch, inputs, swe, steps=200, reps=5):
+    """The 128 x 64 dam break (Section 2.1): ms per step, graph replays of
+    all its steps, median of reps runs after one untimed run."""
+    sc = inputs.dam_break()
+    stream = torch.cuda.Stream()
+    times = []
+    for r in range(reps + 1):
+        s = swe.Solver.from_scenario(sc, stream=stream)
+        s.set_option(swe.OPT_GRAPH_STEPS, steps)
+        s.step(steps)  # builds and runs the graph once
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        s.step(steps)
+        b.record(stream)
+        b.synchronize()
+        if r:
+            times.append(a.elapsed_time(b) / steps)
+        s.close()
+    times.sort()
+    ms = times[len(times) // 2]
+    res = {"workload": f"dam_break {sc.params.nx}x{sc.params.ny}", "steps": steps,
+           "ms_per_step": ms, "cell_updates_per_s": sc.cells / (ms * 1e-3)}
+    log(f"small grid: {res}")
+    return res
 
 
 def measure_outputs(s, torch, stream, sc, steps=300, chunk=25, n_out=6):
@@ -385,6 +414,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true", help="skip the ensemble and serving runs")
     ap.add_argument("--no-outputs", action="store_true", help="skip the snapshot/max-depth measurement")
+    ap.add_argument("--no-small-grid", action="store_true", help="skip the 128 x 64 latency measurement")
     ap.add_argument("--ens-count", type=int, default=64)
     ap.add_argument("--ens-steps", type=int, default=3000)
     ap.add_argument("--serve-requests", type=int, default=48)
@@ -427,6 +457,8 @@ def main():
     }
     if outputs is not None:
         out["outputs"] = outputs
+    if not args.no_small_grid:
+        out["small_grid"] = measure_small_grid(torch, inputs, swe)
     if not args.no_batched:
         batched, members = run_batched(args, torch, inputs, swe)
         out["batched"] = batched
