@@ -288,7 +288,7 @@ def run_serving(args, swe, members, capacity_per_s):
     mean_steps = float(np.mean(steps))
     rate = 0.7 * capacity_per_s * args.ens_steps / mean_steps  # requests per second
     gaps = rng.exponential(1.0 / rate, size=n)
-    sv = swe.Server(mem_budget=args.serve_budget_gb << 30, max_slots=64, segment_steps=100)
+    sv = swe.Server(mem_budget=args.serve_budget_gb << 30, max_slots=args.serve_slots, segment_steps=100)
     sv.set_mode(swe.BATCH_ROUNDS)
     t_start = time.perf_counter()
     t_next = t_start
@@ -322,7 +322,7 @@ def run_serving(args, swe, members, capacity_per_s):
             "p99_time_to_result_s": float(np.percentile(ttr, 99)),
             "scenarios_per_hour": len(ok) / span * 3600.0,
             "mem_budget_bytes": st["mem_budget"], "mem_high_water_bytes": st["mem_high_water"],
-            "segments": st["segments"]}
+            "max_slots": args.serve_slots, "segments": st["segments"]}
 
 
 def run_uneven(args, torch, inputs, swe):
@@ -420,6 +420,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-steps", type=int, default=1000)
     ap.add_argument("--serve-budget-gb", type=int, default=2)
+    ap.add_argument("--serve-slots", type=int, default=64,
+                    help="requests resident and stepped together (the server's max_slots)")
     ap.add_argument("--workload", choices=("coast", "uneven", "serving"), default="coast",
                     help="coast: the main line (default); uneven: the 200-scenario uneven batch; "
                          "serving: Poisson serving at --serve-loads of capacity")

@@ -4,13 +4,13 @@
 // FIFO queue; a request is admitted when a slot is free and its footprint
 // (swe_footprint) fits a first-fit hole of the arena, so admission is by HBM
 // footprint and never calls hipMalloc or hipFree.  Resident scenarios advance
-// together in segments: one persistent launch advances every resident
-// scenario by min(segment_steps, its remaining steps).  While a segment runs,
-// the thread uploads newly admitted requests on a copy stream and copies the
-// results of scenarios finished in the previous segment back to host memory;
-// those scenarios then leave the arena.  Requests that arrive while others are
-// on the GPU therefore join the mix at the next segment boundary, and their
-// work overlaps with that of the requests already running.  Every scenario
+// together in segments: one launch sequence advances every resident scenario
+// by min(segment_steps, its remaining steps).  While a segment runs, the
+// thread prepares and uploads newly admitted requests on a copy stream and
+// copies the results of scenarios finished in the previous segment back to
+// host memory; those scenarios then leave the arena, and the uploaded ones
+// join at the next segment.  The compute stream therefore never waits for
+// host-side preparation or transfers while resident work remains.  Every scenario
 // runs the same per-tile stage code as alone, so its result does not depend
 // on what else is in the mix.
 #include <hip/hip_runtime.h>
@@ -187,19 +187,6 @@ void swe_server::loop()
                 continue;
             }
         }
-        // upload admitted requests (copy stream) and make them resident
-        for (Request *r : admitted) {
-            const int rc = scenario_upload_into(r->d.base, r->p, r->f, copy, r->d);
-            std::lock_guard<std::mutex> lk(mu);
-            r->f = HostFields();
-            if (rc) {
-                arena.release(r->d.base, scenario_bytes(r->p.nx, r->p.ny));
-                r->d.base = nullptr;
-                finish(r, SWE_FAILED, rc);
-            } else {
-                active.push_back(r);
-            }
-        }
         // one segment over every resident scenario with steps left
         std::vector<Geo> geos;
         std::vector<int> ks;
@@ -228,7 +215,22 @@ void swe_server::loop()
             ++segments;
             if (rc) fatal = rc;
         }
-        // while the segment runs: results of the previous segment's finishers
+        // while the segment runs: upload the admitted requests (copy stream;
+        // they join at the next segment) ...
+        std::vector<Request *> joining;
+        for (Request *r : admitted) {
+            const int urc = scenario_upload_into(r->d.base, r->p, r->f, copy, r->d);
+            std::lock_guard<std::mutex> lk(mu);
+            r->f = HostFields();
+            if (urc) {
+                arena.release(r->d.base, scenario_bytes(r->p.nx, r->p.ny));
+                r->d.base = nullptr;
+                finish(r, SWE_FAILED, urc);
+            } else {
+                joining.push_back(r);
+            }
+        }
+        // ... and copy out the results of the previous segment's finishers
         for (Request *r : retiring) {
             int rrc = SWE_OK;
             if (!r->cancel) {
@@ -277,6 +279,7 @@ void swe_server::loop()
                 keep.push_back(r);
             }
         }
+        keep.insert(keep.end(), joining.begin(), joining.end());
         active.swap(keep);
     }
     // shutdown: drop whatever is resident
