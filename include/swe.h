@@ -202,6 +202,15 @@ int swe_batch_set_mode(swe_batch *bt, int32_t mode, int32_t use_graph);
 /* Tile variant used by the batch's launches (-1: automatic, from the
  * scenario with most cells).  All variants give bitwise identical states. */
 int swe_batch_set_tile(swe_batch *bt, int32_t tile);
+/* Maximum-depth map of scenario `index`, as swe_track_max_depth for a
+ * single scenario: with enable != 0 keep per cell the maximum of h over its
+ * state at the call and after every later step of this batch (the map is
+ * updated inside the batch's own stage launches); enable = 0 drops it.
+ * SWE_ENOTFOUND for a bad index, SWE_ENOMEM if the plane cannot be
+ * allocated.  swe_batch_read_max_depth waits for the batch's stream and
+ * copies the map ([ny][nx]); SWE_EINVAL if it is not being kept. */
+int swe_batch_track_max_depth(swe_batch *bt, int32_t index, int32_t enable);
+int swe_batch_read_max_depth(swe_batch *bt, int32_t index, float *hmax);
 void swe_batch_destroy(swe_batch *bt);
 
 /* ---- serving: continuous batching of scenario requests ------------------ */

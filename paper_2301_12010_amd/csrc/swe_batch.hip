@@ -293,6 +293,7 @@ struct BatchScen {
     DevScenario d;
     int total = 0;  // requested steps
     int done = 0;   // steps enqueued so far
+    float *hmax = nullptr;  // maximum-depth plane, when tracked
 };
 
 struct swe_batch {
@@ -398,11 +399,52 @@ int swe_batch_read(swe_batch *bt, int32_t index, float *h, float *hu, float *hv,
     return scenario_read(bt->sc[index].d, bt->stream, h, hu, hv, st);
 }
 
+int swe_batch_track_max_depth(swe_batch *bt, int32_t index, int32_t enable)
+{
+    if (!bt) return SWE_EINVAL;
+    if (index < 0 || index >= (int)bt->sc.size()) return SWE_ENOTFOUND;
+    BatchScen &s = bt->sc[index];
+    if (s.hmax) {
+        SWE_HIP_TRY(hipStreamSynchronize(bt->stream));
+        (void)hipFree(s.hmax);
+        s.hmax = nullptr;
+        s.d.geo.hmax = nullptr;
+    }
+    if (!enable) return SWE_OK;
+    const Geo &g = s.d.geo;
+    const size_t bytes = (size_t)g.pitch * g.ny * sizeof(float);
+    if (hipMalloc(&s.hmax, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        s.hmax = nullptr;
+        return SWE_ENOMEM;
+    }
+    // start from the current depth, after the work already enqueued
+    SWE_HIP_TRY(hipMemcpyAsync(s.hmax, g.U[0], bytes, hipMemcpyDeviceToDevice, bt->stream));
+    s.d.geo.hmax = s.hmax;
+    return SWE_OK;
+}
+
+int swe_batch_read_max_depth(swe_batch *bt, int32_t index, float *hmax)
+{
+    if (!bt || !hmax) return SWE_EINVAL;
+    if (index < 0 || index >= (int)bt->sc.size()) return SWE_ENOTFOUND;
+    const BatchScen &s = bt->sc[index];
+    if (!s.hmax) return SWE_EINVAL;
+    const Geo &g = s.d.geo;
+    const size_t row = (size_t)g.nx * sizeof(float), spitch = (size_t)g.pitch * sizeof(float);
+    SWE_HIP_TRY(hipMemcpy2DAsync(hmax, row, s.hmax, spitch, row, g.ny, hipMemcpyDeviceToHost, bt->stream));
+    SWE_HIP_TRY(hipStreamSynchronize(bt->stream));
+    return SWE_OK;
+}
+
 void swe_batch_destroy(swe_batch *bt)
 {
     if (!bt) return;
     if (bt->stream) (void)hipStreamSynchronize(bt->stream);
-    for (auto &s : bt->sc) scenario_free(s.d);
+    for (auto &s : bt->sc) {
+        if (s.hmax) (void)hipFree(s.hmax);
+        scenario_free(s.d);
+    }
     if (bt->own_stream && bt->stream) (void)hipStreamDestroy(bt->stream);
     delete bt;  // the segment launcher frees its tables
 }

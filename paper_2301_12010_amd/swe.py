@@ -100,6 +100,8 @@ _SIGS = {
     "swe_batch_read": (ctypes.c_int, [_VP, ctypes.c_int32, _FP, _FP, _FP, ctypes.POINTER(Stats)]),
     "swe_batch_set_mode": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "swe_batch_set_tile": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "swe_batch_track_max_depth": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
+    "swe_batch_read_max_depth": (ctypes.c_int, [_VP, ctypes.c_int32, _FP]),
     "swe_batch_destroy": (None, [_VP]),
     "swe_server_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_size_t, ctypes.c_int32,
                                          ctypes.c_int32, ctypes.POINTER(_VP)]),
@@ -362,6 +364,16 @@ class Batch:
         st = Stats()
         rc = _lib().swe_batch_read(self._bt, int(index), None, None, None, ctypes.byref(st))
         return st.as_dict() | {"rc": rc}
+
+    def track_max_depth(self, index: int, enable: bool = True):
+        _check(_lib().swe_batch_track_max_depth(self._bt, int(index), int(bool(enable))),
+               "swe_batch_track_max_depth")
+
+    def max_depth(self, index: int):
+        ny, nx = self._shapes[index]
+        hm = np.empty((ny, nx), np.float32)
+        _check(_lib().swe_batch_read_max_depth(self._bt, int(index), hm.ctypes.data), "swe_batch_read_max_depth")
+        return hm
 
     def close(self):
         if getattr(self, "_bt", None):

@@ -131,3 +131,35 @@ def test_output_requests_validated_and_replaced():
     s.step(2)
     assert s.read()[3]["step"] == 5
     s.close()
+
+
+@pytest.mark.parametrize("mode", [swe.BATCH_ROUNDS, swe.BATCH_PERSISTENT])
+def test_batch_max_depth_equals_alone(mode):
+    # maximum-depth maps of ensemble members kept inside the batch's launches
+    mix = [(inputs.random_wet(130, 70, seed=11, dry_fraction=0.05), 9),
+           (inputs.nwave_beach(nx=256, ny=32, dx=8.0), 12),
+           (inputs.random_wet(40, 24, seed=12), 0)]
+    bt = swe.Batch()
+    bt.set_mode(mode, True)
+    for i, (sc, n) in enumerate(mix):
+        bt.add_scenario(sc, n)
+        if i != 1:
+            bt.track_max_depth(i)
+    bt.track_max_depth(1)   # also on the last one, then restarted below
+    bt.track_max_depth(1, False)
+    bt.track_max_depth(1, True)
+    bt.run(4)
+    bt.run()
+    for i, (sc, n) in enumerate(mix):
+        s = swe.Solver.from_scenario(sc)
+        s.track_max_depth(True)
+        s.step(n)
+        ref = s.max_depth()
+        s.close()
+        got = bt.max_depth(i)
+        assert np.array_equal(got, ref), i
+    assert np.array_equal(bt.max_depth(2), mix[2][0].h)  # no steps: the start
+    bt.track_max_depth(0, False)
+    with pytest.raises(swe.SweError):
+        bt.max_depth(0)
+    bt.close()
