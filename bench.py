@@ -89,9 +89,47 @@ def cpu_baseline(sc, budget_s=15.0):
         if el >= budget_s or steps >= 50 or el * (steps + 1) / steps > 2 * budget_s:
             break
     rate = sc.cells * steps / el
-    return {"value": rate, "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"FP64 checker, {sc.params.nx}x{sc.params.ny} large coastline, first {steps} "
-                      f"RK3 step(s) from the same initial state ({el:.1f} s)"}
+    o.close()
+    out = {"value": rate, "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"FP64 checker, {sc.params.nx}x{sc.params.ny} large coastline, first {steps} "
+                     f"RK3 step(s) from the same initial state ({el:.1f} s)",
+           "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
+    one = _cpu_one_thread(sc)
+    if one is not None:
+        out["one_thread"] = one
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _cpu_one_thread(sc):
+    """The checker on one thread: its first step of the same grid, in a child
+    process (the OpenMP thread count is fixed when the runtime starts)."""
+    import subprocess
+    code = ("import sys, time, json; sys.path.insert(0, %r); import oracle; "
+            "from paper_2301_12010_amd import inputs; "
+            "sc = inputs.large_coast(%d, %d, %r, seed=2); o = oracle.Oracle.from_scenario(sc); "
+            "t = time.perf_counter(); o.step(1); el = time.perf_counter() - t; "
+            "print(json.dumps({'value': sc.cells / el, 'seconds': el, 'threads': oracle.num_threads()}))"
+            % (ROOT, sc.params.nx, sc.params.ny, sc.params.dx))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+        res = json.loads(r.stdout.strip().splitlines()[-1])
+        res.update({"unit": UNIT, "sample": "FP64 checker, first RK3 step of the same grid, one thread"})
+        return res
+    except Exception as exc:  # the baseline is a report; its absence is stated
+        log(f"one-thread baseline skipped: {exc}")
+        return None
 
 
 def run_large(args, torch, inputs, swe):
