@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2301_12010_amd import swe
@@ -57,6 +58,40 @@ def test_host_only_calls():
     L.swe_destroy(None)
     L.swe_batch_destroy(None)
     L.swe_server_destroy(None)
+    assert L.swe_set_outputs(None, None, 0) == swe.EINVAL
+    assert L.swe_output_get(None, 0, 0, None, None, None, None, None) == swe.EINVAL
+    assert L.swe_track_max_depth(None, 1) == swe.EINVAL
+    assert L.swe_read_max_depth(None, None) == swe.EINVAL
+    assert L.swe_batch_track_max_depth(None, 0, 1) == swe.EINVAL
+    assert L.swe_batch_read_max_depth(None, 0, None) == swe.EINVAL
+
+
+def test_create_rejects_bad_sizes_before_reading_fields():
+    # parameters are validated before any field is read or any device call
+    # is made: a 1-element dummy array stands for every field
+    import ctypes
+    dummy = np.zeros(1, np.float32)
+    ptr = dummy.ctypes.data
+    out = ctypes.c_void_p()
+
+    def create(**kw):
+        base = dict(nx=8, ny=8, dx=1.0, dy=1.0, g=9.81, cfl=0.4, dt_fixed=0.0, h_dry=1e-3,
+                    weno_eps=1e-6, kappa_cap=0.0, bc=(0, 0, 0, 0))
+        base.update(kw)
+        p = swe.make_params(base)
+        return swe.lib().swe_create(ctypes.byref(p), ptr, ptr, ptr, ptr, ptr, None, ctypes.byref(out))
+
+    assert create(nx=2) == swe.EINVAL and create(ny=0) == swe.EINVAL
+    # planes of 2^30 elements or more (rows padded to 64) are refused
+    assert create(nx=32768, ny=32768) == swe.EINVAL
+    assert create(nx=32705, ny=32768) == swe.EINVAL   # pitch 32768
+    assert create(nx=3, ny=(1 << 30) // 64) == swe.EINVAL  # pitch 64
+    assert create(dx=0.0) == swe.EINVAL and create(dy=-1.0) == swe.EINVAL
+    assert create(g=float("nan")) == swe.EINVAL
+    assert create(cfl=0.0, dt_fixed=0.0) == swe.EINVAL
+    assert create(weno_eps=0.0) == swe.EINVAL
+    assert create(bc=(0, 0, 0, 7)) == swe.EINVAL
+    assert out.value is None
 
 
 def test_params_struct_layout_matches_header():

@@ -184,3 +184,38 @@ def test_invalid_inputs_and_nonfinite():
         s.read()
     assert ei.value.code == swe.ENONFINITE
     s.close()
+
+
+@pytest.mark.parametrize("nx,ny", [(3, 3), (3, 40), (40, 3)])
+def test_minimum_and_thin_grids(nx, ny):
+    # every cell within three cells of a wall: the halo is mostly mirror
+    sc = inputs.random_wet(nx, ny, seed=nx * 100 + ny)
+    g, st, r, rs = run_both(sc, 4)
+    e = field_errors(g, r)
+    say("thin", nx, ny, e)
+    assert max(e) <= TOL_SMOOTH and st["step"] == 4
+
+
+def test_anisotropic_cells():
+    sc = inputs.random_wet(64, 40, seed=21, dx=2.0, dy=0.5)
+    g, st, r, rs = run_both(sc, 5)
+    e = field_errors(g, r)
+    say("anisotropic", e)
+    assert max(e) <= TOL_SMOOTH
+    assert abs(st["t"] - rs["t"]) <= 1e-6 * rs["t"]
+
+
+def test_all_dry_domain_stays_still():
+    # no water anywhere: both wave speeds vanish, dt = 0, nothing moves
+    sc = inputs.random_wet(50, 30, seed=22)
+    z = np.zeros_like(sc.h)
+    s = swe.Solver(sc.params, sc.b, sc.n, z, z, z)
+    s.step(5)
+    h, hu, hv, st = s.read()
+    s.close()
+    o = oracle.Oracle(sc.params, sc.b, sc.n, z, z, z)
+    assert o.step(5) == 0
+    rs = o.scalars()
+    assert np.all(h == 0) and np.all(hu == 0) and np.all(hv == 0)
+    assert st["t"] == 0.0 and rs["t"] == 0.0 and st["step"] == 5
+    assert st["status"] == swe.OK and st["mass"] == 0.0
