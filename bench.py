@@ -57,10 +57,10 @@ def log(*a):
 
 
 def kernel_source_digest():
+    """Digest of the stage kernel's source (its body and launch wrapper)."""
     h = hashlib.sha256()
-    for f in ("swe_stage.hpp", "swe_core.hip"):
-        with open(os.path.join(ROOT, "paper_2301_12010_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_2301_12010_amd", "csrc", "swe_stage.hpp"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -16,23 +16,6 @@ namespace swe {
 // kernels
 // ---------------------------------------------------------------------------
 
-// Blocks are dispatched round-robin over the 8 XCDs; renumber them so that
-// each XCD receives a contiguous band of tiles and shares halo rows in its L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb)
-{
-    const int q = nb >> 3, r = nb & 7;
-    const int x = b & 7, l = b >> 3;
-    return x * q + (x < r ? x : r) + l;
-}
-
-template <class C, int S, int W>
-__global__ __launch_bounds__(C::NT, W) void k_stage(Geo G, int ntx, int nblocks)
-{
-    __shared__ float lds[C::LDS_FLOATS];
-    const int id = xcd_remap(blockIdx.x, nblocks);
-    stage_tile<C, (W <= 2)>(G, id % ntx, id / ntx, lds, S);
-}
-
 // Wave speeds (slot 0) and runup of the initial state.
 __global__ __launch_bounds__(256) void k_init(Geo G)
 {
@@ -601,9 +584,14 @@ static int outputs_post(swe_ctx *c)
     return SWE_OK;
 }
 
+// Destroys the captured step graph after any launch of it has finished (the
+// buffers it refers to may be released next).
 static void drop_graph(swe_ctx *c)
 {
-    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->graph) {
+        if (c->stream) (void)hipStreamSynchronize(c->stream);
+        (void)hipGraphExecDestroy(c->graph);
+    }
     c->graph = nullptr;
     c->graph_k = 0;
 }

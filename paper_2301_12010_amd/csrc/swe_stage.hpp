@@ -717,4 +717,22 @@ __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *
     stage_publish<C>(G, sc, acc, tx == 0 && ty == 0, lds);
 }
 
+// Blocks are dispatched round-robin over the 8 XCDs; renumber them so that
+// each XCD receives a contiguous band of tiles and shares halo rows in its L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, l = b >> 3;
+    return x * q + (x < r ? x : r) + l;
+}
+
+// The stage kernel: one tile per block.
+template <class C, int S, int W>
+__global__ __launch_bounds__(C::NT, W) void k_stage(Geo G, int ntx, int nblocks)
+{
+    __shared__ float lds[C::LDS_FLOATS];
+    const int id = xcd_remap(blockIdx.x, nblocks);
+    stage_tile<C, (W <= 2)>(G, id % ntx, id / ntx, lds, S);
+}
+
 }  // namespace swe
