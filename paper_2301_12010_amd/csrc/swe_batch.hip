@@ -158,7 +158,7 @@ struct BatchKernels {
 // same order as the single-scenario variant table
 static const BatchKernels g_bk[] = {SWE_BK(64, 16, 8, 2) SWE_BK(64, 32, 8, 2) SWE_BK(32, 32, 8, 2)
                                         SWE_BK(64, 16, 4, 2) SWE_BK(128, 16, 8, 2) SWE_BK(64, 16, 4, 3)
-                                            SWE_BK(32, 32, 4, 3)};
+                                            SWE_BK(32, 32, 4, 3) SWE_BK(32, 16, 2, 2) SWE_BK(16, 16, 2, 2) SWE_BK(16, 16, 1, 2)};
 
 // ---------------------------------------------------------------------------
 // segment launcher (shared by swe_batch and the server)

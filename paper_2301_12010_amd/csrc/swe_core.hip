@@ -183,7 +183,10 @@ static int launch_snap(const Geo &g, const double *times, SnapMeta *m, float *sl
     X(64, 16, 4, 2)      \
     X(128, 16, 8, 2)     \
     X(64, 16, 4, 3)      \
-    X(32, 32, 4, 3)
+    X(32, 32, 4, 3)      \
+    X(32, 16, 2, 2)      \
+    X(16, 16, 2, 2)      \
+    X(16, 16, 1, 2)
 
 #define SWE_VARIANT(TX, TY, R, W)                                                           \
     {TX, TY, R, TileCfg<TX, TY, R>::NT, W, sizeof(float) * TileCfg<TX, TY, R>::LDS_FLOATS, \
