@@ -22,11 +22,25 @@
 namespace swe {
 
 static std::mutex g_tune_mu;
+
+// First variant with this tile shape (0 if none: every variant is correct).
+static int variant_by_shape(int tx, int ty, int r)
+{
+    for (int i = 0; i < variant_count(); ++i) {
+        const Variant &v = variant(i);
+        if (v.tx == tx && v.ty == ty && v.r == r) return i;
+    }
+    return 0;
+}
 static std::map<std::pair<int, int>, int> g_tuned;
 
-// Built-in choice when nothing was tuned for this size: the 128x16 tile
-// (256 threads, 8 cells per thread per sweep) measured fastest on MI355X for
-// 1024^2 and 4096^2 grids.
+// Built-in choice when nothing was tuned for this size.  With 256 or more
+// 128x16 tiles (about one per CU and more) that tile (256 threads, 8 cells per
+// thread per sweep) measured fastest on MI355X (1024x512 to 4096^2).  Smaller
+// grids leave most CUs idle and a stage lasts one block's critical path,
+// which tiles with fewer cells per thread shorten: 64x16 with 4 cells per
+// thread from 64 tiles (512^2: 4.95e9 vs 4.20e9 cell-updates/s), 32x16 with 2
+// below (256^2: 1.74e9 vs 1.09e9).
 int default_variant(int nx, int ny)
 {
     {
@@ -34,7 +48,9 @@ int default_variant(int nx, int ny)
         auto it = g_tuned.find({nx, ny});
         if (it != g_tuned.end()) return it->second;
     }
-    return 4;
+    const long long tiles = (long long)((nx + 127) / 128) * ((ny + 15) / 16);
+    if (tiles >= 256) return variant_by_shape(128, 16, 8);
+    return tiles >= 64 ? variant_by_shape(64, 16, 4) : variant_by_shape(32, 16, 2);
 }
 
 static std::string arch_name()
