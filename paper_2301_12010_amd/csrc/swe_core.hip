@@ -460,6 +460,7 @@ struct OutputSet {
     hipEvent_t ev_meta[2] = {nullptr, nullptr};
     bool meta_pending[2] = {false, false};
     int meta_turn = 0;
+    bool post_owed = false;        // steps enqueued since the last metadata copy
     int known = 0;                 // outputs known to be taken
     std::vector<SnapHeader> hdr;   // headers of taken outputs
     std::vector<hipEvent_t> ev_copy;
@@ -568,7 +569,9 @@ static int outputs_service(swe_ctx *c, bool block)
     return SWE_OK;
 }
 
-// After new steps: copy the metadata to a free pinned buffer.
+// After new steps (or when a copy is owed): copy the metadata to a free
+// pinned buffer.  With both buffers in flight the copy is owed and made by
+// the next swe_step or swe_output_get call that finds a buffer free.
 static int outputs_post(swe_ctx *c)
 {
     OutputSet &o = c->out;
@@ -578,12 +581,16 @@ static int outputs_post(swe_ctx *c)
     int b = o.meta_turn;
     if (o.meta_pending[b]) {
         b ^= 1;
-        if (o.meta_pending[b]) return SWE_OK;  // both in flight: the next call posts
+        if (o.meta_pending[b]) {
+            o.post_owed = true;
+            return SWE_OK;
+        }
     }
     SWE_HIP_TRY(hipMemcpyAsync(o.h_meta[b], o.d_meta, snap_meta_bytes(o.n), hipMemcpyDeviceToHost, c->stream));
     SWE_HIP_TRY(hipEventRecord(o.ev_meta[b], c->stream));
     o.meta_pending[b] = true;
     o.meta_turn = b ^ 1;
+    o.post_owed = false;
     return SWE_OK;
 }
 
@@ -745,7 +752,7 @@ int swe_output_get(swe_ctx *c, int32_t k, int32_t wait, float *h, float *hu, flo
 {
     if (!c || k < 0 || k >= c->out.n) return SWE_EINVAL;
     OutputSet &o = c->out;
-    int rc = outputs_service(c, false);
+    int rc = o.post_owed ? outputs_post(c) : outputs_service(c, false);
     if (rc) return rc;
     if (!o.queued[k] && wait) {
         // everything enqueued so far: wait for it and read the metadata

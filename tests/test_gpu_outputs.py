@@ -163,3 +163,28 @@ def test_batch_max_depth_equals_alone(mode):
     with pytest.raises(swe.SweError):
         bt.max_depth(0)
     bt.close()
+
+
+def test_outputs_reach_the_host_by_non_blocking_polls_alone():
+    # many back-to-back swe_step calls keep both metadata copies in flight;
+    # the copies they owe are made by later polls, so polling without waiting
+    # delivers a snapshot taken in the last steps
+    import time
+    sc = inputs.random_wet(64, 48, seed=13)
+    t = step_times(sc, 30)
+    s = swe.Solver.from_scenario(sc)
+    s.set_outputs([0.5 * (t[27] + t[28])])
+    for _ in range(30):
+        s.step(1)
+    got, deadline = None, time.time() + 30.0
+    while got is None and time.time() < deadline:
+        got = s.output(0, wait=False)
+        time.sleep(0.001)
+    assert got is not None and got[4] == 29
+    h, hu, hv, st = s.read()
+    s.close()
+    ref = swe.Solver.from_scenario(sc)
+    ref.step(29)
+    rh = ref.read()
+    ref.close()
+    assert all(np.array_equal(a, b) for a, b in zip(got[:3], rh[:3]))
