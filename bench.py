@@ -369,41 +369,54 @@ def run_serving(args, swe, members, capacity_per_s):
 
 
 def run_uneven(args, torch, inputs, swe):
-    """Uneven batch: 200 scenarios of four grid sizes and U{1000..4000} steps."""
+    """Uneven batch: 200 scenarios of four grid sizes and U{1000..4000} steps,
+    tiles autotuned per size class; per-round launches and the persistent
+    kernel, each captured as a graph, against the plain solver."""
     plan = inputs.uneven_plan(args.uneven_count)
     t0 = time.perf_counter()
-    bt = swe.Batch()
-    cells_steps = 0
-    by_size = {}
+    scens, by_size, cells_steps = [], {}, 0
     for s_idx, ((nx, ny), steps) in enumerate(plan):
-        sc = inputs.uneven_scenario(s_idx, plan)
-        bt.add_scenario(sc)
+        scens.append(inputs.uneven_scenario(s_idx, plan))
         cells_steps += nx * ny * steps
         by_size.setdefault((nx, ny), []).append((s_idx, steps))
         if s_idx % 20 == 0:
-            log(f"uneven: generated and uploaded {s_idx + 1}/{len(plan)}")
-    log(f"uneven: {len(plan)} scenarios ready in {time.perf_counter() - t0:.1f}s")
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    bt.run()
-    for i in range(len(plan)):
-        st = bt.stats(i)
-        assert st["rc"] == 0 and st["step"] == plan[i][1], (i, st)
-    dt = time.perf_counter() - t
-    bt.close()
-    out = {"workload": f"uneven_batch_{len(plan)}", "scenarios": len(plan),
-           "cell_updates": cells_steps, "seconds": dt, "cell_updates_per_s": cells_steps / dt,
-           "scenarios_per_hour": len(plan) / dt * 3600.0,
-           "sizes": {f"{nx}x{ny}": len(v) for (nx, ny), v in by_size.items()}}
-    log(f"uneven batched: {dt:.1f}s, {cells_steps / dt:.3e} cell-updates/s")
-    # plain solver, one scenario at a time: two members of each size class,
-    # per-cell-update rate of the class applied to all of its members
+            log(f"uneven: generated {s_idx + 1}/{len(plan)}")
+    tiles = {}
+    for (nx, ny) in by_size:
+        tiles[f"{nx}x{ny}"] = swe.autotune(nx, ny)[0]
+    log(f"uneven: {len(plan)} scenarios ready in {time.perf_counter() - t0:.1f}s, tuned tiles {tiles}")
+    out = {"workload": f"uneven_batch_{len(plan)}", "scenarios": len(plan), "cell_updates": cells_steps,
+           "sizes": {f"{nx}x{ny}": len(v) for (nx, ny), v in by_size.items()},
+           "tuned_tile_variants": tiles}
+    for name, mode in (("rounds_graph", swe.BATCH_ROUNDS), ("persistent_graph", swe.BATCH_PERSISTENT)):
+        bt = swe.Batch()
+        bt.set_mode(mode, True)
+        for sc in scens:
+            bt.add_scenario(sc)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        bt.run()
+        for i in range(len(plan)):
+            st = bt.stats(i)
+            assert st["rc"] == 0 and st["step"] == plan[i][1], (i, st)
+        dt = time.perf_counter() - t
+        bt.close()
+        out[name] = {"seconds": dt, "cell_updates_per_s": cells_steps / dt,
+                     "scenarios_per_hour": len(plan) / dt * 3600.0}
+        log(f"uneven {name}: {dt:.1f}s, {cells_steps / dt:.3e} cell-updates/s")
+    best = max(("rounds_graph", "persistent_graph"), key=lambda k: out[k]["scenarios_per_hour"])
+    out["mode"] = best
+    out["seconds"] = out[best]["seconds"]
+    out["cell_updates_per_s"] = out[best]["cell_updates_per_s"]
+    out["scenarios_per_hour"] = out[best]["scenarios_per_hour"]
+    # plain solver, one scenario at a time with its size's tuned tile: two
+    # members of each size class, the class's per-cell-update rate applied to
+    # all of its members
     plain_s = 0.0
     for (nx, ny), members in by_size.items():
         rates = []
         for s_idx, steps in members[:2]:
-            sc = inputs.uneven_scenario(s_idx, plan)
-            sol = swe.Solver.from_scenario(sc)
+            sol = swe.Solver.from_scenario(scens[s_idx])
             sol.stats()
             t = time.perf_counter()
             sol.step(steps)
