@@ -97,7 +97,36 @@ def cpu_baseline(sc, budget_s=15.0):
     one = _cpu_one_thread(sc)
     if one is not None:
         out["one_thread"] = one
+    out["per_config"] = _cpu_per_config()
     return out
+
+
+def _cpu_per_config():
+    """The checker (all threads) on the other workloads' truncated samples:
+    the dam break in full, three ensemble members for 50 steps, one uneven
+    member per size class for 20 steps."""
+    import oracle
+    from paper_2301_12010_amd import inputs
+
+    def rate(scens, steps):
+        cells, t = 0, 0.0
+        for sc in scens:
+            o = oracle.Oracle.from_scenario(sc)
+            t0 = time.perf_counter()
+            o.step(steps)
+            t += time.perf_counter() - t0
+            o.close()
+            cells += sc.cells * steps
+        return {"value": cells / t, "unit": UNIT, "seconds": t}
+
+    plan = inputs.uneven_plan()
+    picks = [next(i for i, (sz, _) in enumerate(plan) if sz == size) for size in inputs.UNEVEN_SIZES]
+    return {
+        "dam_break_128x64_200_steps": rate([inputs.dam_break()], 200),
+        "ensemble_3_members_1024x1024_50_steps":
+            rate([inputs.mitigation_coast(1024, 1024, 2.0, seed=1000 + k) for k in range(3)], 50),
+        "uneven_one_per_size_20_steps": rate([inputs.uneven_scenario(i, plan) for i in picks], 20),
+    }
 
 
 def _cpu_model():
