@@ -5,9 +5,9 @@ replays and the autotuned tile, as bench.py times it.  Element by element
 against the FP64 checker for the first 20 steps (the checker takes about a
 second per step on the host; momentum bounded by the larger of 1e-4 and 1.5x
 the FP32-storage floor of 80 m deep water, see parity.py), and through
-properties that hold at any size over a longer run: mass balance with
-clamping, finite non-negative depths, dry cells without momentum,
-non-decreasing runup.
+properties that hold at any size over the configuration's whole 2000-step
+run: mass balance with clamping, finite non-negative depths, dry cells
+without momentum, non-decreasing runup.
 """
 import sys
 
@@ -62,28 +62,33 @@ def test_large_coast_first_steps_against_checker(coast):
     assert abs(g[3]["t"] - rs["t"]) <= 1e-6 * rs["t"]
 
 
-def test_large_coast_properties_over_200_steps(coast):
+def test_large_coast_properties_over_the_full_run(coast):
+    # the configuration's whole run (2000 steps) in graph replays of 50
     s = swe.Solver.from_scenario(coast)
     s.set_option(swe.OPT_GRAPH_STEPS, 50)
-    m0 = None
+    m0 = s.read()[3]["mass"]
     runup = []
     for k in range(4):
-        h, hu, hv, st = s.read() if k else s.read()
-        if m0 is None:
-            m0 = st["mass"]
+        s.step(500)
+        st = s.read()[3]
         runup.append(st["runup"])
-        s.step(50)
+        say("after", st["step"], "steps", st)
+        assert st["status"] == swe.OK
     h, hu, hv, st = s.read()
     s.close()
-    say("after 200 steps", st)
-    assert st["step"] == 200
+    assert st["step"] == 2000
     for a in (h, hu, hv):
         assert np.all(np.isfinite(a))
     assert np.all(h >= 0.0)
     dry = h <= coast.params.h_dry
     assert np.all(hu[dry] == 0.0) and np.all(hv[dry] == 0.0)
-    # FP64 sum of the FP32 state: mass changes only by clamping, up to FP32
-    # rounding of the updates
-    assert abs(st["mass"] - m0 - st["clamp_mass"]) <= 1e-6 * m0
-    runup.append(st["runup"])
+    # FP64 sum of the FP32 state: mass changes by clamping and by the FP32
+    # rounding of the three stored stage states per step.  That rounding is
+    # not mean-free as waves spread (depth increments below half an ulp are
+    # lost with one sign): the FP64 checker storing only u^(n+1) in FP32
+    # already drifts by 2.5e-10 (flat 80 m water) to 3.8e-10 (this coast at
+    # 512^2) of the mass per step, the GPU by 1.1e-9 here; bound 5e-9 per step
+    drift = (st["mass"] - m0 - st["clamp_mass"]) / m0
+    say("mass balance", drift, "per step", drift / st["step"])
+    assert abs(drift) <= 5e-9 * st["step"]
     assert all(b >= a for a, b in zip(runup, runup[1:]))
