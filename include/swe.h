@@ -113,9 +113,12 @@ void swe_destroy(swe_ctx *ctx);
 #define SWE_OPT_TILE 2        /* tile variant index, see swe_tile_info; -1 = automatic (default) */
 int swe_set_option(swe_ctx *ctx, int32_t key, int64_t value);
 
-/* Device addresses of the context's live state planes (h, hu, hv of u^n)
- * and the row pitch in elements, for callers that keep results on the GPU.
- * The planes change only through swe_step. */
+/* Device addresses of the context's live state (depth h, hu, hv of u^n) and
+ * the row pitch in elements, for callers that keep results on the GPU.  The
+ * library stores the level h + min(b, 0) rather than h (precise surface
+ * elevation in deep water); the h plane returned is a depth copy that this
+ * call refreshes on the context's stream and that stays valid until the next
+ * swe_step.  hu and hv are the live planes and change only through swe_step. */
 int swe_state_device(swe_ctx *ctx, float **h, float **hu, float **hv, int64_t *pitch);
 
 /* Measurement: run nsteps steps with plain launches, bracketing every stage

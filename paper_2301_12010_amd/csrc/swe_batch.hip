@@ -419,7 +419,8 @@ int swe_batch_track_max_depth(swe_batch *bt, int32_t index, int32_t enable)
         return SWE_ENOMEM;
     }
     // start from the current depth, after the work already enqueued
-    SWE_HIP_TRY(hipMemcpyAsync(s.hmax, g.U[0], bytes, hipMemcpyDeviceToDevice, bt->stream));
+    const int drc = launch_depth(g, g.U[0], s.hmax, bt->stream);
+    if (drc) return drc;
     s.d.geo.hmax = s.hmax;
     return SWE_OK;
 }

@@ -1,6 +1,7 @@
 // swe_core.hip - single-scenario context, stage kernels and shared host code.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstddef>
@@ -27,7 +28,8 @@ __global__ __launch_bounds__(256) void k_init(Geo G)
     for (long long e = blockIdx.x * 256ll + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
         const int j = (int)(e / G.nx), i = (int)(e - (long long)j * G.nx);
         const int gi = j * G.pitch + i;
-        const float h = G.U[0][gi], hu = G.U[1][gi], hv = G.U[2][gi];
+        const float b = G.b[gi], lo = fminf(b, 0.f);
+        const float h = G.U[0][gi] - lo, hu = G.U[1][gi], hv = G.U[2][gi];
         const bool wet = h > G.h_dry;
         const float cel = sqrtf(G.g * fmaxf(h, 0.f));
         const float inv = wet ? 1.f / h : 0.f;
@@ -36,8 +38,7 @@ __global__ __launch_bounds__(256) void k_init(Geo G)
         const unsigned int by = fin ? speed_bits(fabsf(hv * inv) + cel) : 0x7f800000u;
         sx = bx > sx ? bx : sx;
         sy = by > sy ? by : sy;
-        hs += (double)h;
-        const float b = G.b[gi];
+        hs += (double)G.U[0][gi] - (double)lo;
         if (wet && b > 0.f) rb = __float_as_uint(b) > rb ? __float_as_uint(b) : rb;
     }
     sx = wave_max_u32(sx);
@@ -78,7 +79,9 @@ __global__ __launch_bounds__(256) void k_mass_part(Geo G)
     const long long n = (long long)G.nx * G.ny;
     for (long long e = blockIdx.x * 256ll + threadIdx.x; e < n; e += (long long)MASS_BLOCKS * 256) {
         const int j = (int)(e / G.nx), i = (int)(e - (long long)j * G.nx);
-        hs += (double)G.U[0][j * G.pitch + i];
+        const int gi = j * G.pitch + i;
+        // depth from the stored level, in FP64
+        hs += (double)G.U[0][gi] - (double)fminf(G.b[gi], 0.f);
     }
     hs = wave_sum_f64(hs);
     if ((threadIdx.x & 63) == 0) rd[threadIdx.x >> 6] = hs;
@@ -102,6 +105,30 @@ int launch_mass(const Geo &g, hipStream_t stream)
     return hipGetLastError() == hipSuccess ? SWE_OK : SWE_EDEVICE;
 }
 
+// Depth h = s - min(b, 0) of a stored-level plane, over whole padded planes
+// (four floats per access: the pitch is a multiple of 64; padding is zero).
+__global__ __launch_bounds__(256) void k_depth(Geo G, const float *lev, float *out)
+{
+    const size_t q = (size_t)G.pitch * G.ny / 4;
+    const float4 *s4 = reinterpret_cast<const float4 *>(lev);
+    const float4 *b4 = reinterpret_cast<const float4 *>(G.b);
+    float4 *o4 = reinterpret_cast<float4 *>(out);
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < q; i += (size_t)gridDim.x * 256) {
+        const float4 a = s4[i], b = b4[i];
+        o4[i] = make_float4(a.x - fminf(b.x, 0.f), a.y - fminf(b.y, 0.f), a.z - fminf(b.z, 0.f),
+                            a.w - fminf(b.w, 0.f));
+    }
+}
+
+int launch_depth(const Geo &g, const float *lev, float *out, hipStream_t stream)
+{
+    const size_t q = (size_t)g.pitch * g.ny / 4;
+    size_t blocks = (q + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_depth, dim3((unsigned)blocks), dim3(256), 0, stream, g, lev, out);
+    return hipGetLastError() == hipSuccess ? SWE_OK : SWE_EDEVICE;
+}
+
 // ---------------------------------------------------------------------------
 // outputs during a run: snapshots at output times, maximum-depth map
 // ---------------------------------------------------------------------------
@@ -122,8 +149,8 @@ struct SnapMeta {
 
 static size_t snap_meta_bytes(int n) { return offsetof(SnapMeta, hdr) + (size_t)n * sizeof(SnapHeader); }
 
-// Copy u^n into output slot `next` if the step just completed reached its
-// time.  Every block takes the same decision: nothing writes `next` or t in
+// Copy u^n (depth, hu, hv) into output slot `next` if the step just
+// completed reached its time.  Every block takes the same decision: nothing writes `next` or t in
 // this kernel.  Planes are copied whole (pitch included), four floats per
 // access (the pitch is a multiple of 64).
 __global__ __launch_bounds__(256) void k_snap_copy(Geo G, const double *times, const SnapMeta *m,
@@ -137,8 +164,11 @@ __global__ __launch_bounds__(256) void k_snap_copy(Geo G, const double *times, c
     const float4 *s0 = reinterpret_cast<const float4 *>(G.U[0]);
     const float4 *s1 = reinterpret_cast<const float4 *>(G.U[1]);
     const float4 *s2 = reinterpret_cast<const float4 *>(G.U[2]);
+    const float4 *b4 = reinterpret_cast<const float4 *>(G.b);
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < q; i += (size_t)gridDim.x * 256) {
-        dst[i] = s0[i];
+        const float4 a = s0[i], b = b4[i];  // depth from the stored level
+        dst[i] = make_float4(a.x - fminf(b.x, 0.f), a.y - fminf(b.y, 0.f), a.z - fminf(b.z, 0.f),
+                             a.w - fminf(b.w, 0.f));
         dst[q + i] = s1[i];
         dst[2 * q + i] = s2[i];
     }
@@ -296,8 +326,10 @@ std::vector<float> build_ghosts(const swe_params &p, const HostFields &f)
                 else if (side == 2) { i0 = q; j0 = 0; i1 = q; j1 = 1; }
                 else { i0 = q; j0 = ny - 1; i1 = q; j1 = ny - 2; }
                 const double b0 = at(f.b, i0, j0), b1 = at(f.b, i1, j1);
-                const float vals[4] = {at(f.h, i0, j0), at(f.hu, i0, j0), at(f.hv, i0, j0),
-                                       (float)(b0 + (k + 1) * (b0 - b1))};
+                const float bg = (float)(b0 + (k + 1) * (b0 - b1));
+                // the frozen depth stored as a level over the ghost's own bed
+                const float sg = (float)((double)at(f.h, i0, j0) + std::min((double)bg, 0.0));
+                const float vals[4] = {sg, at(f.hu, i0, j0), at(f.hv, i0, j0), bg};
                 for (int fld = 0; fld < 4; ++fld) g[base + (size_t)(fld * 3 + k) * len + q] = vals[fld];
             }
     }
@@ -354,14 +386,17 @@ int scenario_upload_into(void *mem, const swe_params &p, const HostFields &f, hi
     g.hmax = nullptr;
 
     const size_t N = (size_t)nx * ny;
-    std::vector<float> gn2(N);
-    for (size_t k = 0; k < N; ++k) gn2[k] = (float)(p.g * (double)f.n[k] * (double)f.n[k]);
+    std::vector<float> gn2(N), s0(N);
+    for (size_t k = 0; k < N; ++k) {
+        gn2[k] = (float)(p.g * (double)f.n[k] * (double)f.n[k]);
+        s0[k] = (float)((double)f.h[k] + std::min((double)f.b[k], 0.0));  // stored level
+    }
     std::vector<float> gh = build_ghosts(p, f);
     const size_t row = (size_t)nx * sizeof(float), dpitch = (size_t)pitch * sizeof(float);
     SWE_HIP_TRY(hipMemsetAsync(base, 0, 11 * plane, stream));
     SWE_HIP_TRY(hipMemcpy2DAsync(planes[0], dpitch, f.b.data(), row, row, ny, hipMemcpyHostToDevice, stream));
     SWE_HIP_TRY(hipMemcpy2DAsync(planes[1], dpitch, gn2.data(), row, row, ny, hipMemcpyHostToDevice, stream));
-    SWE_HIP_TRY(hipMemcpy2DAsync(planes[2], dpitch, f.h.data(), row, row, ny, hipMemcpyHostToDevice, stream));
+    SWE_HIP_TRY(hipMemcpy2DAsync(planes[2], dpitch, s0.data(), row, row, ny, hipMemcpyHostToDevice, stream));
     SWE_HIP_TRY(hipMemcpy2DAsync(planes[3], dpitch, f.hu.data(), row, row, ny, hipMemcpyHostToDevice, stream));
     SWE_HIP_TRY(hipMemcpy2DAsync(planes[4], dpitch, f.hv.data(), row, row, ny, hipMemcpyHostToDevice, stream));
     SWE_HIP_TRY(hipMemcpyAsync(ghost, gh.data(), gh.size() * sizeof(float), hipMemcpyHostToDevice, stream));
@@ -427,9 +462,15 @@ int scenario_read(const DevScenario &d, hipStream_t stream, float *h, float *hu,
     const Geo &g = d.geo;
     const size_t row = (size_t)g.nx * sizeof(float), spitch = (size_t)g.pitch * sizeof(float);
     float *outs[3] = {h, hu, hv};
+    const float *src[3] = {g.A[0], g.U[1], g.U[2]};
+    if (h) {
+        // depth from the stored level into u^(1)'s first plane, free between steps
+        const int rc = launch_depth(g, g.U[0], g.A[0], stream);
+        if (rc) return rc;
+    }
     for (int c = 0; c < 3; ++c)
         if (outs[c])
-            SWE_HIP_TRY(hipMemcpy2DAsync(outs[c], row, g.U[c], spitch, row, g.ny, hipMemcpyDefault, stream));
+            SWE_HIP_TRY(hipMemcpy2DAsync(outs[c], row, src[c], spitch, row, g.ny, hipMemcpyDefault, stream));
     int rc = launch_mass(g, stream);
     if (rc) return rc;
     DevScen ds;
@@ -810,7 +851,8 @@ int swe_track_max_depth(swe_ctx *c, int32_t enable)
         return SWE_ENOMEM;
     }
     // start from the current depth, after the work already enqueued
-    SWE_HIP_TRY(hipMemcpyAsync(c->d_hmax, g.U[0], bytes, hipMemcpyDeviceToDevice, c->stream));
+    const int drc = launch_depth(g, g.U[0], c->d_hmax, c->stream);
+    if (drc) return drc;
     c->d.geo.hmax = c->d_hmax;
     return SWE_OK;
 }
@@ -846,7 +888,13 @@ int swe_set_option(swe_ctx *c, int32_t key, int64_t value)
 int swe_state_device(swe_ctx *c, float **h, float **hu, float **hv, int64_t *pitch)
 {
     if (!c) return SWE_EINVAL;
-    if (h) *h = c->d.geo.U[0];
+    if (h) {
+        // the depth is derived from the stored level: refreshed into u^(1)'s
+        // first plane, which no call but swe_step overwrites
+        const int rc = launch_depth(c->d.geo, c->d.geo.U[0], c->d.geo.A[0], c->stream);
+        if (rc) return rc;
+        *h = c->d.geo.A[0];
+    }
     if (hu) *hu = c->d.geo.U[1];
     if (hv) *hv = c->d.geo.U[2];
     if (pitch) *pitch = c->d.geo.pitch;

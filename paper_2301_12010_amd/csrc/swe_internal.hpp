@@ -71,6 +71,8 @@ struct Variant {
     size_t lds_bytes;
     void (*stage[3])(Geo, int, int);  // single-scenario stage kernels
 };
+// depth h = s - min(b, 0) of a stored-level plane into out (same pitch)
+int launch_depth(const Geo &g, const float *lev, float *out, hipStream_t stream);
 int variant_count();
 const Variant &variant(int i);
 int default_variant(int nx, int ny);

@@ -7,9 +7,10 @@
 // Manning sources of Eqs. (2)-(3).
 //
 // Work layout, per block:
-//   1. the tile's input state (h, hu, hv, b) with a 3-cell cross-shaped halo
-//      is staged in LDS with coalesced row loads; ghosts are mirrored or read
-//      from frozen planes on the fly, so no separate ghost pass exists;
+//   1. the tile's input state (s, hu, hv, b) with a 3-cell cross-shaped halo
+//      is staged in LDS with coalesced row loads (s is the stored level, see
+//      Geo); ghosts are mirrored or read from frozen planes on the fly, so no
+//      separate ghost pass exists;
 //   2. x sweep: each thread walks R consecutive cells of one row, keeping a
 //      3-cell window of split fluxes in registers.  Every cell centre's
 //      second and first differences, the three smoothness indicators and the
@@ -61,8 +62,13 @@ struct Geo {
     float kappa_cap, cfl, dt_fixed;
     int pad;
     const float *b, *gn2;    // bed and g n^2 planes
-    float *U[3], *A[3], *B[3];      // u^n, u^(1), u^(2): h, hu, hv planes
-    const float *ghost;      // frozen FIXED ghosts, see ghost_index()
+    // u^n, u^(1), u^(2): planes of (s, hu, hv) where s = h + min(b, 0) is the
+    // stored level: the surface elevation h + b where the bed lies below the
+    // datum, the depth h on land.  In deep water s stays small, so FP32 keeps
+    // the surface to ~1e-7 m instead of an ulp of the depth (8e-6 m at 80 m),
+    // and thin films on land keep their own precision.
+    float *U[3], *A[3], *B[3];
+    const float *ghost;      // frozen FIXED ghosts (s, hu, hv, b), see ghost_index()
     DevScen *sd;
     double *mass_part;       // MASS_BLOCKS partial sums of the mass kernel
     float *hmax;             // maximum-depth plane (same pitch), or null
@@ -144,7 +150,7 @@ __device__ __forceinline__ float wt(float beta12, float kd, float ek)
 // the bed term -g (h+b)(bhat_{k+1/2} - bhat_{k-1/2})/ds on the momentum
 // component normal to the faces.
 template <int R, int DIR, class Emit>
-__device__ __forceinline__ void sweep(const float *__restrict__ Lh, const float *__restrict__ Lhu,
+__device__ __forceinline__ void sweep(const float *__restrict__ Ls, const float *__restrict__ Lhu,
                                       const float *__restrict__ Lhv, const float *__restrict__ Lb,
                                       int li0, int st, const SweepK &K, Emit &&emit)
 {
@@ -170,10 +176,12 @@ __device__ __forceinline__ void sweep(const float *__restrict__ Lh, const float 
 #pragma unroll
     for (int w = -HALO; w < R + HALO; ++w) {
         const int li = li0 + (w + HALO) * st;
-        const float h = Lh[li], hu = Lhu[li], hv = Lhv[li], b = Lb[li];
+        const float sv = Ls[li], hu = Lhu[li], hv = Lhv[li], b = Lb[li];
+        // depth and surface elevation from the stored level (see Geo)
+        const float h = sv - fminf(b, 0.f);
+        const float e = sv + fmaxf(b, 0.f);
         // cell flux, LF split vector u~ = (h+b, hu, hv) and the split fluxes
         const float inv = h > K.h_dry ? frcp(h) : 0.f;
-        const float e = h + b;
         const float pres = K.half_g * (h - b) * e;
         float F0, F1, F2;
         if (DIR == 0) {
@@ -492,7 +500,7 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
 {
     constexpr int TX = C::TX, TY = C::TY, R = C::R;
     const int STAGE = sc.stage;
-    const float *Lh = lds, *Lhu = lds + C::PLANE, *Lhv = lds + 2 * C::PLANE, *Lb = lds + 3 * C::PLANE;
+    const float *Ls = lds, *Lhu = lds + C::PLANE, *Lhv = lds + 2 * C::PLANE, *Lb = lds + 3 * C::PLANE;
     float *Xr = lds + 4 * C::PLANE;
     const int tid = threadIdx.x;
     const int x0 = tx * TX, y0 = ty * TY;
@@ -514,7 +522,7 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
         K.hinv_ds = 0.5f * G.inv_dx;
         K.ghinv_ds = -G.g * K.hinv_ds;
         float *xo = Xr + row * C::XR + seg * R;
-        sweep<R, 0>(Lh, Lhu, Lhv, Lb, (row + HALO) * C::SX + seg * R, 1, K,
+        sweep<R, 0>(Ls, Lhu, Lhv, Lb, (row + HALO) * C::SX + seg * R, 1, K,
                     [&](int k, float l0, float l1, float l2) {
                         xo[k] = l0;
                         xo[C::XPLANE + k] = l1;
@@ -548,7 +556,7 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
     K.a = sc.ay;
     K.hinv_ds = 0.5f * G.inv_dy;
     K.ghinv_ds = -G.g * K.hinv_ds;
-    sweep<R, 1>(Lh, Lhu, Lhv, Lb, (seg * R) * C::SX + col + HALO, C::SX, K,
+    sweep<R, 1>(Ls, Lhu, Lhv, Lb, (seg * R) * C::SX + col + HALO, C::SX, K,
                 [&](int k, float l0, float l1, float l2) {
                     res[k][0] = l0;
                     res[k][1] = l1;
@@ -564,7 +572,9 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
         const unsigned gi = (unsigned)(gy * pitch + gx);
         const int li = (ly + HALO) * C::SX + col + HALO;
         const int xi = ly * C::XR + col;
-        const float h = Lh[li], hu = Lhu[li], hv = Lhv[li];
+        const float sv = Ls[li], hu = Lhu[li], hv = Lhv[li], bb = Lb[li];
+        const float lo = fminf(bb, 0.f);  // level of zero depth
+        const float h = sv - lo;
         float Lh_ = Xr[xi] + res[k][0];
         float Lhu_ = Xr[C::XPLANE + xi] + res[k][1];
         float Lhv_ = Xr[2 * C::XPLANE + xi] + res[k][2];
@@ -577,9 +587,11 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
             Lhu_ = fmaf(-kap, hu, Lhu_);
             Lhv_ = fmaf(-kap, hv, Lhv_);
         }
-        float oh = fmaf(dt, Lh_, h), ohu = fmaf(dt, Lhu_, hu), ohv = fmaf(dt, Lhv_, hv);
+        // the combination acts on the stored level: it differs from the depth
+        // by a per-cell constant and the stage weights sum to one
+        float os = fmaf(dt, Lh_, sv), ohu = fmaf(dt, Lhu_, hu), ohv = fmaf(dt, Lhv_, hv);
         if (STAGE == 2) {
-            oh = fmaf(0.75f, PF ? pun[k][0] : pld(G.U[0], gi), 0.25f * oh);
+            os = fmaf(0.75f, PF ? pun[k][0] : pld(G.U[0], gi), 0.25f * os);
             ohu = fmaf(0.75f, PF ? pun[k][1] : pld(G.U[1], gi), 0.25f * ohu);
             ohv = fmaf(0.75f, PF ? pun[k][2] : pld(G.U[2], gi), 0.25f * ohv);
         }
@@ -590,20 +602,22 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
             const float un0 = PF ? pun[k][0] : pld(G.U[0], gi);
             const float un1 = PF ? pun[k][1] : pld(G.U[1], gi);
             const float un2 = PF ? pun[k][2] : pld(G.U[2], gi);
-            oh = fmaf(2.f / 3.f, oh - un0, un0);
+            os = fmaf(2.f / 3.f, os - un0, un0);
             ohu = fmaf(2.f / 3.f, ohu - un1, un1);
             ohv = fmaf(2.f / 3.f, ohv - un2, un2);
         }
+        float oh = os - lo;
         if (oh < 0.f) {
             acc.deficit -= oh;
             oh = 0.f;
+            os = lo;
         }
         const bool wet = oh > h_dry;
         if (!wet) {
             ohu = 0.f;
             ohv = 0.f;
         }
-        pst(O[0], gi, oh);
+        pst(O[0], gi, os);
         pst(O[1], gi, ohu);
         pst(O[2], gi, ohv);
         if (STAGE == 3 && G.hmax) {
@@ -619,7 +633,6 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
         acc.sxb = bx > acc.sxb ? bx : acc.sxb;
         acc.syb = by > acc.syb ? by : acc.syb;
         if (STAGE == 3) {
-            const float bb = Lb[li];
             if (wet && bb > 0.f) {
                 const unsigned int u = __float_as_uint(bb);
                 acc.rub = u > acc.rub ? u : acc.rub;
