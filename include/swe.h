@@ -118,12 +118,15 @@ int swe_set_option(swe_ctx *ctx, int32_t key, int64_t value);
  * library stores the level h + min(b, 0) rather than h (precise surface
  * elevation in deep water); the h plane returned is a depth copy that this
  * call refreshes on the context's stream and that stays valid until the next
- * swe_step.  hu and hv are the live planes and change only through swe_step. */
+ * swe_step or swe_time_stages.  hu and hv are the live planes and change only
+ * through those two calls. */
 int swe_state_device(swe_ctx *ctx, float **h, float **hu, float **hv, int64_t *pitch);
 
 /* Measurement: run nsteps steps with plain launches, bracketing every stage
  * kernel with HIP events on the context's stream; ms[0..2] receive the mean
- * device duration of the stage-1, -2 and -3 launches.  Blocks until done. */
+ * device duration of the stage-1, -2 and -3 launches.  Blocks until done.
+ * The steps advance the state as swe_step does (requested outputs are taken,
+ * a tracked maximum-depth map is updated). */
 int swe_time_stages(swe_ctx *ctx, int32_t nsteps, double *ms);
 
 /* ---- outputs during a run ------------------------------------------------

@@ -919,6 +919,9 @@ int swe_time_stages(swe_ctx *c, int32_t nsteps, double *ms)
             if (!rc) rc = launch_stage(v, st + 1, c->d.geo, c->stream);
             if (!rc && hipEventRecord(ev[2 * st + 1], c->stream) != hipSuccess) rc = SWE_EDEVICE;
         }
+        // the timed steps are ordinary steps: outputs requested are still taken
+        if (!rc && c->out.n > 0)
+            rc = launch_snap(c->d.geo, c->out.d_times, c->out.d_meta, c->out.d_slots, c->stream);
         if (!rc && hipEventSynchronize(ev[5]) != hipSuccess) rc = SWE_EDEVICE;
         for (int st = 0; st < 3 && !rc; ++st) {
             float t = 0.f;
@@ -928,7 +931,7 @@ int swe_time_stages(swe_ctx *c, int32_t nsteps, double *ms)
     }
     for (int k = 0; k < 6; ++k) (void)hipEventDestroy(ev[k]);
     for (int st = 0; st < 3; ++st) ms[st] = acc[st] / nsteps;
-    return rc;
+    return rc ? rc : outputs_post(c);
 }
 
 int swe_tile_count(void) { return variant_count(); }

@@ -188,3 +188,28 @@ def test_outputs_reach_the_host_by_non_blocking_polls_alone():
     rh = ref.read()
     ref.close()
     assert all(np.array_equal(a, b) for a, b in zip(got[:3], rh[:3]))
+
+
+def test_timed_steps_take_outputs_like_plain_steps():
+    # the measurement call advances the state like swe_step: the snapshot and
+    # the maximum-depth map equal those of the same steps taken plainly
+    sc = inputs.random_wet(64, 48, seed=14)
+    t = step_times(sc, 10)
+    times = [0.5 * (t[4] + t[5])]
+    runs = []
+    for timed in (True, False):
+        s = swe.Solver.from_scenario(sc)
+        s.set_outputs(times)
+        s.track_max_depth(True)
+        if timed:
+            s.time_stages(10)
+        else:
+            s.step(10)
+        runs.append((s.output(0, wait=True), s.max_depth(), s.read()))
+        s.close()
+    (snap_a, hmax_a, st_a), (snap_b, hmax_b, st_b) = runs
+    assert snap_a is not None and snap_a[4] == snap_b[4] == 6
+    assert all(np.array_equal(a, b) for a, b in zip(snap_a[:3], snap_b[:3]))
+    assert np.array_equal(hmax_a, hmax_b)
+    assert all(np.array_equal(a, b) for a, b in zip(st_a[:3], st_b[:3]))
+    assert st_a[3]["step"] == 10
