@@ -210,7 +210,35 @@ def run_large(args, torch, inputs, swe):
     other = roof_hbm if roofline is roof_alu else roof_alu
     outputs = None if args.no_outputs else measure_outputs(s, torch, stream, sc)
     s.close()
-    return sc, value, ms, roofline, other, tv, outputs
+    e2e = None if args.no_end_to_end else measure_end_to_end(swe, stream, sc, tile, args)
+    return sc, value, ms, roofline, other, tv, outputs, e2e
+
+
+def measure_end_to_end(swe, stream, sc, tile, args):
+    """The same job from host arrays to host arrays: swe_create from the host
+    fields (validation, ghosts, upload over PCIe), the timed steps, and
+    swe_read of h, hu, hv into host memory.  Reported beside `value`, never
+    as it: `value` starts with the state resident in HBM."""
+    import time as _t
+    t0 = _t.perf_counter()
+    s = swe.Solver.from_scenario(sc, stream=stream)
+    s.set_option(swe.OPT_TILE, tile)
+    s.set_option(swe.OPT_GRAPH_STEPS, args.graph_steps)
+    s.stats()  # upload complete
+    t1 = _t.perf_counter()
+    s.step(args.steps)
+    s.stats()
+    t2 = _t.perf_counter()
+    h, hu, hv, st = s.read()
+    t3 = _t.perf_counter()
+    s.close()
+    if st["status"] != 0:
+        raise RuntimeError(f"end-to-end run non-finite: {st}")
+    rate = sc.cells * args.steps / (t3 - t0)
+    log(f"end to end: create {t1 - t0:.3f}s, steps {t2 - t1:.3f}s, read {t3 - t2:.3f}s -> {rate:.3e}")
+    return {"value": rate, "unit": UNIT, "create_s": t1 - t0, "steps_s": t2 - t1, "read_s": t3 - t2,
+            "steps": args.steps,
+            "note": "host fields -> swe_create -> steps -> swe_read to host; host clock"}
 
 
 def measure_small_grid(torch, inputs, swe, steps=200, reps=5):
@@ -499,6 +527,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true", help="skip the ensemble and serving runs")
     ap.add_argument("--no-outputs", action="store_true", help="skip the snapshot/max-depth measurement")
+    ap.add_argument("--no-end-to-end", action="store_true",
+                    help="skip the host-to-host run (create from host fields, steps, read to host)")
     ap.add_argument("--no-small-grid", action="store_true", help="skip the 128 x 64 latency measurement")
     ap.add_argument("--ens-count", type=int, default=64)
     ap.add_argument("--ens-steps", type=int, default=3000)
@@ -531,7 +561,7 @@ def main():
     if args.workload == "serving":
         print(json.dumps(run_serving_scale(args, torch, inputs, swe)), flush=True)
         return
-    sc, value, ms, roofline, other, tv, outputs = run_large(args, torch, inputs, swe)
+    sc, value, ms, roofline, other, tv, outputs, e2e = run_large(args, torch, inputs, swe)
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
@@ -542,6 +572,8 @@ def main():
                    "tile": [tv["tx"], tv["ty"], tv["r"]], "graph_steps": args.graph_steps},
         "roofline": roofline, "roofline_other": other,
     }
+    if e2e is not None:
+        out["end_to_end"] = e2e
     if outputs is not None:
         out["outputs"] = outputs
     if not args.no_small_grid:
