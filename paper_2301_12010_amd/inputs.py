@@ -270,6 +270,28 @@ def large_coast(nx: int = 4096, ny: int = 4096, dx: float = 5.0, seed: int = 2,
                     _f32(hv), nsteps, dict(seed=seed, xs=xs))
 
 
+def deep_ocean(nx: int = 96, ny: int = 64, dx: float = 1000.0, seed: int = 5,
+               depth: float = 4000.0, nseamounts: int = 6) -> Scenario:
+    """Open-ocean propagation: a 4 km deep basin with seeded seamounts and
+    trenches (amplitude U(-800, 800) m, radius U(5, 15) km) and a 1 m
+    Gaussian hump of 8 km radius.  Fully wet and smooth; in FP32 an ocean
+    depth has an ulp of 2.4e-4 m, so this case shows whether the stored
+    state resolves a metre-scale wave on top of it."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X, Y = _centres(nx, ny, dx, dx)
+    Lx, Ly = nx * dx, ny * dx
+    b = np.full((ny, nx), -depth)
+    for _ in range(nseamounts):
+        b = b + _gauss(X, Y, rng.uniform(-800.0, 800.0), rng.uniform(5e3, 15e3),
+                       rng.uniform(0, Lx), rng.uniform(0, Ly))
+    eta = _gauss(X, Y, 1.0, 8e3, 0.3125 * Lx, 0.5 * Ly)
+    h, hu, hv = _wet_state(eta, b, 1e-3)
+    n = np.full((ny, nx), 0.025)
+    p = Params(nx, ny, dx, dx, cfl=0.4, h_dry=1e-3, kappa_cap=1.0)
+    return Scenario(f"deep_ocean_{nx}x{ny}", p, _f32(b), _f32(n), _f32(h), _f32(hu),
+                    _f32(hv), 0, dict(seed=seed, depth=depth))
+
+
 def mitigation_coast(nx: int = 1024, ny: int = 1024, dx: float = 2.0, seed: int = 1000,
                      nsteps: int = 3000) -> Scenario:
     """One mitigation-ensemble member: beach + coastal hills + Manning patches.

@@ -22,6 +22,7 @@ CASES = {
     "mitigation_256_s1000": lambda: inputs.mitigation_coast(256, 256, 2.0, seed=1000),
     "mitigation_1024_s1003": lambda: inputs.mitigation_coast(1024, 1024, 2.0, seed=1003),
     "uneven_s7": lambda: inputs.uneven_scenario(7),
+    "deep_ocean_s5": lambda: inputs.deep_ocean(),
 }
 
 

@@ -144,6 +144,18 @@ def test_lake_at_rest_fp32_roundoff():
     assert eta_hist[-1] <= 4 * max(eta_hist[0], 1e-6)
 
 
+def test_deep_ocean_smooth():
+    # a metre-scale wave over a 4 km basin with seamounts: the stored level
+    # (the surface elevation at sea) keeps FP32 rounding at the wave's scale,
+    # not at the ulp of a 4 km depth (2.4e-4 m)
+    sc = inputs.deep_ocean()
+    g, st, r, rs = run_both(sc, 60, graph_steps=20)
+    e = field_errors(g, r)
+    say("deep ocean errors", e, "max |hu|", float(np.abs(r[1]).max()))
+    assert max(e) <= TOL_SMOOTH
+    assert st["step"] == 60 and abs(st["t"] - rs["t"]) <= 1e-6 * rs["t"]
+
+
 def test_torch_device_buffers_and_stream():
     import torch
     sc = inputs.random_wet(40, 30, seed=21)
