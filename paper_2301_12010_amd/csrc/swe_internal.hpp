@@ -35,7 +35,8 @@ int load_fields(const swe_params *p, const float *b, const float *n, const float
 inline int plane_pitch(int nx) { return (nx + 63) / 64 * 64; }
 
 // Frozen FIXED ghosts (see ghost_index in swe_stage.hpp): (h, hu, hv) of the
-// nearest interior cell, b extended linearly from the two nearest cells.
+// nearest interior cell, b extended linearly from the two nearest cells; the
+// depth is stored as the level h + min(b, 0) over the ghost's own bed.
 std::vector<float> build_ghosts(const swe_params &p, const HostFields &f);
 
 // Device storage of one scenario: 11 planes + ghosts + DevScen in one block.

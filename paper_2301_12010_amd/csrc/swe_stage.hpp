@@ -74,7 +74,7 @@ struct Geo {
     float *hmax;             // maximum-depth plane (same pitch), or null
 };
 
-// Frozen ghosts of a FIXED side: [field h,hu,hv,b][layer 0..2][position along the side].
+// Frozen ghosts of a FIXED side: [field s,hu,hv,b][layer 0..2][position along the side].
 // West/east sides have length ny and start at 0 and 12*ny; south/north have
 // length nx and start at 24*ny and 24*ny + 12*nx.
 __device__ __forceinline__ int ghost_index(const Geo &G, int side, int field, int layer, int pos)
