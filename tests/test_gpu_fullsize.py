@@ -123,10 +123,12 @@ def test_mitigation_ensemble_over_the_full_run():
             s.close()
             assert all(np.array_equal(a, b) for a, b in zip((h, hu, hv), ref[:3])), i
     bt.close()
-    # FP32 storage of the level at depths of a few metres (ulp 2.4e-7 m at
-    # 2 m) loses sub-ulp increments with a consistent sign while waves
-    # spread: 2.3e-11 (median) to 2.6e-11 (worst member) of the mass per
-    # step here, against 2.7e-13 on the 80 m deep coastline.  Bound 1e-10.
+    # FP32 storage of the level in a few metres of water: 2.3e-11 (median)
+    # to 2.6e-11 (worst member) of the mass per step here, against 2.7e-13
+    # on the 80 m deep coastline.  The FP64 checker restarted every step
+    # from its level rounded to FP32 drifts by 2.8e-11 per step on the same
+    # coast at 256 x 256 (2.8e-10 when the depth is rounded instead), so
+    # this is the storage precision, not the scheme.  Bound 1e-10.
     worst = max(abs(d) for d in drifts)
     say("ensemble mass drift per step: worst", worst / 3000, "median", sorted(map(abs, drifts))[32] / 3000)
     assert worst <= 1e-10 * 3000
