@@ -242,12 +242,13 @@ typedef struct swe_result {
 typedef struct swe_server_stats {
     int64_t submitted, completed, failed, cancelled, queued, active;
     size_t mem_in_use, mem_high_water, mem_budget;
-    int64_t segments;  /* persistent launches so far */
+    int64_t segments;  /* segments run so far */
 } swe_server_stats;
 
 /* Start a server on `device` with a device-memory budget for scenario state
- * (bytes; 0 = 80% of free memory), at most max_slots resident scenarios, and
- * segment_steps steps per persistent launch between admissions. */
+ * (bytes; 0 = half of the device's free memory), at most max_slots resident
+ * scenarios, and segment_steps steps per segment (one batched run of every
+ * resident request) between admissions. */
 int swe_server_create(int32_t device, size_t mem_budget, int32_t max_slots,
                       int32_t segment_steps, swe_server **out);
 
@@ -263,6 +264,25 @@ int swe_submit(swe_server *sv, const swe_params *p, const float *b, const float 
  * status (DONE, FAILED, CANCELLED) has been returned once; afterwards it is
  * SWE_ENOTFOUND. */
 int swe_poll(swe_server *sv, uint64_t ticket, swe_result *r, float *h, float *hu, float *hv);
+
+/* Flags of swe_submit_ex. */
+#define SWE_SUBMIT_MAX_DEPTH 1 /* keep the request's maximum-depth (inundation) map */
+
+/* swe_submit with flags.  SWE_SUBMIT_MAX_DEPTH keeps, on the device, the
+ * per-cell maximum of the depth over the starting state and the state after
+ * every step (as swe_track_max_depth does for one scenario; Section 3 output
+ * of the paper's runs), adding one plane (4 bytes per cell) to the request's
+ * footprint.  Unknown flags: SWE_EINVAL. */
+int swe_submit_ex(swe_server *sv, const swe_params *p, const float *b, const float *manning_n,
+                  const float *h0, const float *hu0, const float *hv0, int32_t nsteps, int32_t flags,
+                  uint64_t *ticket);
+
+/* swe_poll that also copies the maximum-depth map ([ny][nx], host memory)
+ * into hmax when the request is DONE.  hmax may be NULL; a non-NULL hmax for
+ * a request submitted without SWE_SUBMIT_MAX_DEPTH returns SWE_EINVAL and
+ * leaves the ticket unchanged. */
+int swe_poll_ex(swe_server *sv, uint64_t ticket, swe_result *r, float *h, float *hu, float *hv,
+                float *hmax);
 
 /* Launch mode of the server's segments (SWE_BATCH_ROUNDS, the default, or
  * SWE_BATCH_PERSISTENT); takes effect at the next segment. */

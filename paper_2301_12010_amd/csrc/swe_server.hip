@@ -103,14 +103,23 @@ struct Request {
     int status = SWE_PENDING;
     int error = SWE_OK;
     bool cancel = false;
+    bool track_max = false;  // keep the maximum-depth map (SWE_SUBMIT_MAX_DEPTH)
     double t_submit = 0, t_admit = 0, t_done = 0;
     // resident state
     DevScenario d;
     int done_steps = 0;
     // result
     swe_stats st{};
-    std::vector<float> h, hu, hv;
+    std::vector<float> h, hu, hv, hmax;
 };
+
+// Device bytes of a request: its scenario, plus one plane for the
+// maximum-depth map when it keeps one.
+static size_t request_bytes(const swe_params &p, bool track_max)
+{
+    const size_t plane = ((size_t)plane_pitch(p.nx) * p.ny * sizeof(float) + 255) / 256 * 256;
+    return scenario_bytes(p.nx, p.ny) + (track_max ? plane : 0);
+}
 
 }  // namespace swe
 
@@ -162,7 +171,7 @@ int swe_server::admit_locked(std::vector<Request *> &admitted)
             finish(r, SWE_CANCELLED, SWE_OK);
             continue;
         }
-        void *mem = arena.alloc(scenario_bytes(r->p.nx, r->p.ny));
+        void *mem = arena.alloc(request_bytes(r->p, r->track_max));
         if (!mem) break;  // FIFO: wait for memory to free up
         queue.pop_front();
         r->d.base = mem;
@@ -219,11 +228,17 @@ void swe_server::loop()
         // they join at the next segment) ...
         std::vector<Request *> joining;
         for (Request *r : admitted) {
-            const int urc = scenario_upload_into(r->d.base, r->p, r->f, copy, r->d);
+            int urc = scenario_upload_into(r->d.base, r->p, r->f, copy, r->d);
+            if (!urc && r->track_max) {
+                // the map's plane follows the scenario; it starts at the depth
+                r->d.geo.hmax = reinterpret_cast<float *>(static_cast<char *>(r->d.base) +
+                                                          scenario_bytes(r->p.nx, r->p.ny));
+                urc = launch_depth(r->d.geo, r->d.geo.U[0], r->d.geo.hmax, copy);
+            }
             std::lock_guard<std::mutex> lk(mu);
             r->f = HostFields();
             if (urc) {
-                arena.release(r->d.base, scenario_bytes(r->p.nx, r->p.ny));
+                arena.release(r->d.base, request_bytes(r->p, r->track_max));
                 r->d.base = nullptr;
                 finish(r, SWE_FAILED, urc);
             } else {
@@ -238,10 +253,20 @@ void swe_server::loop()
                 r->h.resize(N);
                 r->hu.resize(N);
                 r->hv.resize(N);
-                rrc = scenario_read(r->d, copy, r->h.data(), r->hu.data(), r->hv.data(), &r->st);
+                if (r->track_max) {
+                    // ordered before the read's own synchronisation
+                    r->hmax.resize(N);
+                    const size_t row = (size_t)r->p.nx * sizeof(float);
+                    const size_t spitch = (size_t)r->d.geo.pitch * sizeof(float);
+                    if (hipMemcpy2DAsync(r->hmax.data(), row, r->d.geo.hmax, spitch, row, r->p.ny,
+                                         hipMemcpyDeviceToHost, copy) != hipSuccess)
+                        rrc = SWE_EDEVICE;
+                }
+                const int src = scenario_read(r->d, copy, r->h.data(), r->hu.data(), r->hv.data(), &r->st);
+                if (!rrc) rrc = src;
             }
             std::lock_guard<std::mutex> lk(mu);
-            arena.release(r->d.base, scenario_bytes(r->p.nx, r->p.ny));
+            arena.release(r->d.base, request_bytes(r->p, r->track_max));
             r->d.base = nullptr;
             if (r->cancel) finish(r, SWE_CANCELLED, SWE_OK);
             else if (rrc == SWE_OK) finish(r, SWE_DONE, SWE_OK);
@@ -269,7 +294,7 @@ void swe_server::loop()
                 }
             if (out) {
                 if (r->error != SWE_OK && !r->cancel) {
-                    arena.release(r->d.base, scenario_bytes(r->p.nx, r->p.ny));
+                    arena.release(r->d.base, request_bytes(r->p, r->track_max));
                     r->d.base = nullptr;
                     finish(r, SWE_FAILED, r->error);
                 } else {
@@ -323,14 +348,15 @@ int swe_server_create(int32_t device, size_t mem_budget, int32_t max_slots, int3
     return SWE_OK;
 }
 
-int swe_submit(swe_server *sv, const swe_params *p, const float *b, const float *n, const float *h0,
-               const float *hu0, const float *hv0, int32_t nsteps, uint64_t *ticket)
+int swe_submit_ex(swe_server *sv, const swe_params *p, const float *b, const float *n, const float *h0,
+                  const float *hu0, const float *hv0, int32_t nsteps, int32_t flags, uint64_t *ticket)
 {
-    if (!sv || !ticket || nsteps < 0) return SWE_EINVAL;
+    if (!sv || !ticket || nsteps < 0 || (flags & ~SWE_SUBMIT_MAX_DEPTH)) return SWE_EINVAL;
     auto r = std::make_unique<Request>();
     int rc = load_fields(p, b, n, h0, hu0, hv0, r->f);
     if (rc) return rc;
-    if (scenario_bytes(p->nx, p->ny) > sv->arena.capacity()) return SWE_ENOMEM;
+    r->track_max = (flags & SWE_SUBMIT_MAX_DEPTH) != 0;
+    if (request_bytes(*p, r->track_max) > sv->arena.capacity()) return SWE_ENOMEM;
     r->p = *p;
     r->nsteps = nsteps;
     r->t_submit = now_seconds();
@@ -345,13 +371,20 @@ int swe_submit(swe_server *sv, const swe_params *p, const float *b, const float 
     return SWE_OK;
 }
 
-int swe_poll(swe_server *sv, uint64_t ticket, swe_result *res, float *h, float *hu, float *hv)
+int swe_submit(swe_server *sv, const swe_params *p, const float *b, const float *n, const float *h0,
+               const float *hu0, const float *hv0, int32_t nsteps, uint64_t *ticket)
+{
+    return swe_submit_ex(sv, p, b, n, h0, hu0, hv0, nsteps, 0, ticket);
+}
+
+int swe_poll_ex(swe_server *sv, uint64_t ticket, swe_result *res, float *h, float *hu, float *hv, float *hmax)
 {
     if (!sv || !res) return SWE_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
     auto it = sv->reqs.find(ticket);
     if (it == sv->reqs.end()) return SWE_ENOTFOUND;
     Request *r = it->second.get();
+    if (hmax && !r->track_max) return SWE_EINVAL;  // no map kept: the ticket stays
     std::memset(res, 0, sizeof *res);
     res->status = r->status;
     res->error = r->error;
@@ -368,9 +401,15 @@ int swe_poll(swe_server *sv, uint64_t ticket, swe_result *res, float *h, float *
         if (h) std::memcpy(h, r->h.data(), N * sizeof(float));
         if (hu) std::memcpy(hu, r->hu.data(), N * sizeof(float));
         if (hv) std::memcpy(hv, r->hv.data(), N * sizeof(float));
+        if (hmax) std::memcpy(hmax, r->hmax.data(), N * sizeof(float));
     }
     sv->reqs.erase(it);  // a final status is reported once
     return SWE_OK;
+}
+
+int swe_poll(swe_server *sv, uint64_t ticket, swe_result *res, float *h, float *hu, float *hv)
+{
+    return swe_poll_ex(sv, ticket, res, h, hu, hv, nullptr);
 }
 
 int swe_server_set_mode(swe_server *sv, int32_t mode)

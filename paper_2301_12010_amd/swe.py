@@ -20,6 +20,7 @@ BC_REFLECT, BC_FIXED = 0, 1
 OPT_GRAPH_STEPS, OPT_TILE = 1, 2
 BATCH_PERSISTENT, BATCH_ROUNDS = 0, 1
 PENDING, DONE, FAILED, CANCELLED = 0, 1, 2, 3
+SUBMIT_MAX_DEPTH = 1
 
 
 class SweError(RuntimeError):
@@ -108,6 +109,9 @@ _SIGS = {
     "swe_submit": (ctypes.c_int, [_VP, ctypes.POINTER(Params), _FP, _FP, _FP, _FP, _FP,
                                   ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
     "swe_poll": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(Result), _FP, _FP, _FP]),
+    "swe_submit_ex": (ctypes.c_int, [_VP, ctypes.POINTER(Params), _FP, _FP, _FP, _FP, _FP,
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
+    "swe_poll_ex": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(Result), _FP, _FP, _FP, _FP]),
     "swe_cancel": (ctypes.c_int, [_VP, ctypes.c_uint64]),
     "swe_server_set_mode": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "swe_server_get_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ServerStats)]),
@@ -398,31 +402,39 @@ class Server:
         self._sv = out
         self._shapes = {}
 
-    def submit(self, params, b, n, h, hu, hv, nsteps: int) -> int:
+    def submit(self, params, b, n, h, hu, hv, nsteps: int, max_depth: bool = False) -> int:
+        """Queue a request; max_depth keeps its maximum-depth map (swe_submit_ex)."""
         p = make_params(params)
         keep = []
         ptrs = [_ptr(a, p.ny, p.nx, keep) for a in (b, n, h, hu, hv)]
         t = ctypes.c_uint64()
-        _check(_lib().swe_submit(self._sv, ctypes.byref(p), *ptrs, int(nsteps), ctypes.byref(t)),
-               "swe_submit")
+        flags = SUBMIT_MAX_DEPTH if max_depth else 0
+        _check(_lib().swe_submit_ex(self._sv, ctypes.byref(p), *ptrs, int(nsteps), flags, ctypes.byref(t)),
+               "swe_submit_ex")
         self._shapes[t.value] = (p.ny, p.nx)
         return t.value
 
-    def submit_scenario(self, sc, nsteps: int | None = None) -> int:
-        return self.submit(sc.params, *sc.fields(), sc.nsteps if nsteps is None else nsteps)
+    def submit_scenario(self, sc, nsteps: int | None = None, max_depth: bool = False) -> int:
+        return self.submit(sc.params, *sc.fields(), sc.nsteps if nsteps is None else nsteps,
+                           max_depth=max_depth)
 
-    def poll(self, ticket: int, want_state: bool = True):
-        """-> (result dict, (h, hu, hv) or None)."""
+    def poll(self, ticket: int, want_state: bool = True, want_max_depth: bool = False):
+        """-> (result dict, (h, hu, hv) or None); with want_max_depth the
+        tuple also holds the maximum-depth map (swe_poll_ex)."""
         r = Result()
         ny, nx = self._shapes.get(ticket, (1, 1))
         arrs = [np.empty((ny, nx), np.float32) for _ in range(3)] if want_state else [None] * 3
+        hmax = np.empty((ny, nx), np.float32) if want_max_depth else None
         ptrs = [a.ctypes.data if a is not None else None for a in arrs]
-        rc = _lib().swe_poll(self._sv, int(ticket), ctypes.byref(r), *ptrs)
-        _check(rc, "swe_poll")
+        rc = _lib().swe_poll_ex(self._sv, int(ticket), ctypes.byref(r), *ptrs,
+                                hmax.ctypes.data if hmax is not None else None)
+        _check(rc, "swe_poll_ex")
         d = r.as_dict()
         if d["status"] != PENDING:
             self._shapes.pop(ticket, None)
-        state = tuple(arrs) if (want_state and d["status"] == DONE) else None
+        state = None
+        if d["status"] == DONE and (want_state or want_max_depth):
+            state = (tuple(arrs) if want_state else ()) + ((hmax,) if want_max_depth else ())
         return d, state
 
     def set_mode(self, mode: int):

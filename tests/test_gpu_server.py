@@ -117,3 +117,51 @@ def test_failures_are_isolated_and_cancel_works():
         sv.poll(t_good)  # released after its final status was reported
     assert ei.value.code == swe.ENOTFOUND
     sv.close()
+
+
+@pytest.mark.parametrize("mode", [swe.BATCH_ROUNDS, swe.BATCH_PERSISTENT])
+def test_served_maximum_depth_maps_equal_alone(mode):
+    # requests that keep their inundation map next to ones that do not; each
+    # map equals the single-scenario map of the same run, bitwise
+    mix = [(inputs.nwave_beach(nx=256, ny=32, dx=8.0), 37, True),
+           (inputs.random_wet(64, 48, seed=31, dry_fraction=0.05), 23, False),
+           (inputs.random_wet(130, 70, seed=32, dry_fraction=0.05), 29, True),
+           (inputs.random_wet(40, 24, seed=33), 0, True)]
+    sv = swe.Server(mem_budget=256 << 20, max_slots=8, segment_steps=7)
+    sv.set_mode(mode)
+    tickets = []
+    for sc, n, keep in mix:
+        tickets.append(sv.submit_scenario(sc, n, max_depth=keep))
+        time.sleep(0.005)
+    # a map asked of a request that keeps none is refused without releasing it
+    with pytest.raises(swe.SweError) as ei:
+        sv.poll(tickets[1], want_max_depth=True)
+    assert ei.value.code == swe.EINVAL
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t, (sc, n, keep) in zip(tickets, mix):
+            if t in out:
+                continue
+            r, st = sv.poll(t, want_max_depth=keep)
+            if r["status"] != swe.PENDING:
+                out[t] = (r, st)
+        assert time.time() - t0 < 60.0, "server did not finish in time"
+        time.sleep(0.002)
+    for t, (sc, n, keep) in zip(tickets, mix):
+        r, state = out[t]
+        assert r["status"] == swe.DONE and r["steps"] == n
+        s = swe.Solver.from_scenario(sc)
+        s.track_max_depth(True)
+        s.step(n)
+        ref = s.read()
+        ref_max = s.max_depth()
+        s.close()
+        assert all(np.array_equal(a, b) for a, b in zip(state[:3], ref[:3])), sc.name
+        if keep:
+            assert len(state) == 4 and np.array_equal(state[3], ref_max), sc.name
+        else:
+            assert len(state) == 3
+    # the map's plane is part of the footprint: nothing stays allocated
+    assert sv.stats()["mem_in_use"] == 0
+    sv.close()
