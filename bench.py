@@ -49,7 +49,7 @@ HBM_PEAK = 8.0e12        # B/s
 # FP32 vector peak: 256 CU x 2.4 GHz x 128 FMA lanes per CU and clock x 2.
 # Plain (unpacked) v_fma_f32 streams sustain 1.5 wave64 instructions per CU
 # and clock on the MI355X (above the 1.0 a 64-lane-per-clock CU would allow),
-# so the published figure, not half of it, is the ceiling for this build.
+# so the published figure, not half of it, is the ceiling for unpacked code.
 FP32_PEAK = 157.3e12
 
 
@@ -552,8 +552,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path; "
+              "every scenario and batch runs on a single device", file=sys.stderr)
         sys.exit(2)
 
     import torch
