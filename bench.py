@@ -432,8 +432,10 @@ def run_serving(args, swe, members, capacity_per_s):
 
 def run_uneven(args, torch, inputs, swe):
     """Uneven batch: 200 scenarios of four grid sizes and U{1000..4000} steps,
-    tiles autotuned per size class; per-round launches and the persistent
-    kernel, each captured as a graph, against the plain solver."""
+    the autotuner run per size class (the batch launches the tile tuned for
+    its largest class; the plain solver uses each class's); per-round
+    launches and the persistent kernel, each captured as a graph, against
+    the plain solver."""
     plan = inputs.uneven_plan(args.uneven_count)
     t0 = time.perf_counter()
     scens, by_size, cells_steps = [], {}, 0

@@ -138,7 +138,8 @@ def test_mitigation_ensemble_over_the_full_run():
 
 def test_uneven_batch_over_the_full_run():
     # the uneven workload as the bench runs it: 200 scenarios of four sizes
-    # with U{1000..4000} steps, tiles autotuned per size, per-round launches
+    # with U{1000..4000} steps, the autotuner run per size (the batch takes
+    # the tile tuned for its largest size), per-round launches
     # captured as a graph.  Every scenario: its own step count, finite state,
     # non-negative depths, motionless dry cells, mass balance; the first
     # scenario of each size bitwise equal to its run alone.
