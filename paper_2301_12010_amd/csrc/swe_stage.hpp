@@ -581,7 +581,9 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
         // explicit Manning friction, wet cells only, rate capped at kappa_cap/dt
         const float gn2 = PF ? pgn2[k] : pld(G.gn2, gi);
         if (h > h_dry && gn2 > 0.f) {
-            const float qn = sqrtf(fmaf(hu, hu, hv * hv));
+            // |q| as a sum of two rounded squares: the same for (hu, hv) and
+            // (hv, hu), so the step commutes with exchanging x and y
+            const float qn = sqrtf(hu * hu + hv * hv);
             const float hm73 = __builtin_amdgcn_exp2f(-2.33333333333333f * __builtin_amdgcn_logf(h));
             const float kap = fminf(gn2 * qn * hm73, sc.kcap);
             Lhu_ = fmaf(-kap, hu, Lhu_);

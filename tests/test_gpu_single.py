@@ -233,14 +233,14 @@ def test_all_dry_domain_stays_still():
     assert st["status"] == swe.OK and st["mass"] == 0.0
 
 
-@pytest.mark.parametrize("dry", [0.0, 0.1])
-def test_transposed_problem_gives_the_transposed_state(dry):
+@pytest.mark.parametrize("dry,manning", [(0.0, 0.0), (0.1, 0.0), (0.1, 0.03)])
+def test_transposed_problem_gives_the_transposed_state(dry, manning):
     # x <-> y exchanged (hu <-> hv): the x and y sweeps perform the same
-    # operations in the same order for each direction and the two parts of
-    # L are added commutatively, so without friction (whose |q| sums hu^2 and
-    # hv^2 in a fixed order) the result is the transposed state, bitwise,
-    # though the tiles are not square
-    sc = inputs.random_wet(70, 45, seed=41, dry_fraction=dry, manning=0.0)
+    # operations in the same order for each direction, the two parts of L
+    # are added commutatively and the friction's |q| is symmetric in hu and
+    # hv, so the result is the transposed state, bitwise, though the tiles
+    # are not square
+    sc = inputs.random_wet(70, 45, seed=41, dry_fraction=dry, manning=manning)
     st = inputs.transpose(sc)
     out = []
     for s_ in (sc, st):
