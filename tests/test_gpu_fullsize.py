@@ -183,9 +183,10 @@ def test_uneven_batch_over_the_full_run():
     # up to 6.1e-10 (256 x 256, 0.5 km of 2 m deep water and beach), 1.9e-10
     # (512 x 1024), 3.6e-11 (1024 x 1024), 5.3e-12 (2048 x 1024), always a
     # gain, while the FP64 checker conserves to 1e-17.  It is not the storage
-    # format (storing the depth everywhere drifts as much); it comes from the
-    # FP32 evaluation of the Lax-Friedrichs mass term where the surface is
-    # near zero (a constant offset of that surface, exact in exact
-    # arithmetic, removes it at this datum).  Bound 1e-9 per step.
+    # format (storing the depth everywhere drifts as much); it shrinks
+    # twentyfold when the surface in the Lax-Friedrichs mass term is offset by
+    # a constant (exact in exact arithmetic) and when the Manning friction is
+    # switched off, so it is an FP32 effect of thin films near the front
+    # whose exact cause is open.  Bound 1e-9 per step.
     worst = abs(drift[order[0]])
     assert worst <= 1e-9
