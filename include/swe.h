@@ -111,6 +111,17 @@ void swe_destroy(swe_ctx *ctx);
 /* Context options (swe_set_option keys). */
 #define SWE_OPT_GRAPH_STEPS 1 /* steps per captured hipGraph segment; 0 = plain launches (default 32) */
 #define SWE_OPT_TILE 2        /* tile variant index, see swe_tile_info; -1 = automatic (default) */
+/* 1: keep the FP32 rounding residual of the stored level in three more
+ * planes (12 bytes per cell) and combine the RK stages with error-free sums,
+ * so that increments below half an ulp of the level are kept; removes the
+ * FP32 mass drift of shallow wet/dry runs (up to 6e-10 of the mass per step
+ * otherwise; about 1e-13 with it).  Costs 8-12 more bytes of traffic per
+ * cell and stage and about 19% more time per step.  0 (default): off.  Can
+ * be switched at any time (the residual then starts at zero; the captured
+ * graph is dropped).  Returns SWE_EINVAL for other values, SWE_ENOMEM when
+ * the planes cannot be allocated (the option is then off).  Contexts only:
+ * batches and servers run without it. */
+#define SWE_OPT_COMPENSATED 3
 int swe_set_option(swe_ctx *ctx, int32_t key, int64_t value);
 
 /* Device addresses of the context's live state (depth h, hu, hv of u^n) and

@@ -82,6 +82,7 @@ __global__ __launch_bounds__(256) void k_mass_part(Geo G)
         const int gi = j * G.pitch + i;
         // depth from the stored level, in FP64
         hs += (double)G.U[0][gi] - (double)fminf(G.b[gi], 0.f);
+        if (G.Rl[0]) hs += (double)G.Rl[0][gi];  // residual of the compensated level
     }
     hs = wave_sum_f64(hs);
     if ((threadIdx.x & 63) == 0) rd[threadIdx.x >> 6] = hs;
@@ -218,9 +219,11 @@ static int launch_snap(const Geo &g, const double *times, SnapMeta *m, float *sl
     X(16, 16, 2, 2)      \
     X(16, 16, 1, 2)
 
-#define SWE_VARIANT(TX, TY, R, W)                                                           \
-    {TX, TY, R, TileCfg<TX, TY, R>::NT, W, sizeof(float) * TileCfg<TX, TY, R>::LDS_FLOATS, \
-     {k_stage<TileCfg<TX, TY, R>, 1, W>, k_stage<TileCfg<TX, TY, R>, 2, W>, k_stage<TileCfg<TX, TY, R>, 3, W>}},
+#define SWE_VARIANT(TX, TY, R, W)                                                                    \
+    {TX, TY, R, TileCfg<TX, TY, R>::NT, W, sizeof(float) * TileCfg<TX, TY, R>::LDS_FLOATS,          \
+     {k_stage<TileCfg<TX, TY, R>, 1, W>, k_stage<TileCfg<TX, TY, R>, 2, W>, k_stage<TileCfg<TX, TY, R>, 3, W>}, \
+     {k_stage<TileCfg<TX, TY, R>, 1, W, true>, k_stage<TileCfg<TX, TY, R>, 2, W, true>,                 \
+      k_stage<TileCfg<TX, TY, R>, 3, W, true>}},
 
 static const Variant g_variants[] = {SWE_TILE_LIST(SWE_VARIANT)};
 
@@ -231,7 +234,8 @@ int launch_stage(const Variant &v, int stage, const Geo &g, hipStream_t stream)
 {
     const int ntx = (g.nx + v.tx - 1) / v.tx, nty = (g.ny + v.ty - 1) / v.ty;
     const int nb = ntx * nty;
-    hipLaunchKernelGGL(v.stage[stage - 1], dim3(nb), dim3(v.nt), 0, stream, g, ntx, nb);
+    hipLaunchKernelGGL(g.Rl[0] ? v.stage_c[stage - 1] : v.stage[stage - 1], dim3(nb), dim3(v.nt), 0, stream, g, ntx,
+                       nb);
     return hipGetLastError() == hipSuccess ? SWE_OK : SWE_EDEVICE;
 }
 
@@ -384,6 +388,7 @@ int scenario_upload_into(void *mem, const swe_params &p, const HostFields &f, hi
     g.sd = reinterpret_cast<DevScen *>(base + 11 * plane + ghost_b);
     g.mass_part = reinterpret_cast<double *>(base + 11 * plane + ghost_b + align256(sizeof(DevScen)));
     g.hmax = nullptr;
+    for (int c = 0; c < 3; ++c) g.Rl[c] = nullptr;
 
     const size_t N = (size_t)nx * ny;
     std::vector<float> gn2(N), s0(N);
@@ -522,6 +527,7 @@ struct swe_ctx {
     OutputSet out;
     hipStream_t copy_stream = nullptr;
     float *d_hmax = nullptr;
+    float *d_resid = nullptr;  // 3 residual planes of the compensated level
 };
 
 static int ctx_tile(const swe_ctx *c)
@@ -733,6 +739,7 @@ void swe_destroy(swe_ctx *c)
     drop_graph(c);
     outputs_free(c);
     if (c->d_hmax) (void)hipFree(c->d_hmax);
+    if (c->d_resid) (void)hipFree(c->d_resid);
     if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
     scenario_free(c->d);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -880,6 +887,28 @@ int swe_set_option(swe_ctx *c, int32_t key, int64_t value)
         if (value < -1 || value >= variant_count()) return SWE_EINVAL;
         c->tile = (int)value;
         drop_graph(c);
+        return SWE_OK;
+    }
+    if (key == SWE_OPT_COMPENSATED) {
+        if (value != 0 && value != 1) return SWE_EINVAL;
+        drop_graph(c);  // captured steps carry the planes' addresses
+        Geo &g = c->d.geo;
+        if (c->d_resid) {
+            SWE_HIP_TRY(hipStreamSynchronize(c->stream));
+            (void)hipFree(c->d_resid);
+            c->d_resid = nullptr;
+            for (int k = 0; k < 3; ++k) g.Rl[k] = nullptr;
+        }
+        if (!value) return SWE_OK;
+        const size_t plane = (size_t)g.pitch * g.ny;
+        if (hipMalloc(&c->d_resid, 3 * plane * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            c->d_resid = nullptr;
+            return SWE_ENOMEM;
+        }
+        // the stored FP32 level is exact as it stands: residuals start at 0
+        SWE_HIP_TRY(hipMemsetAsync(c->d_resid, 0, 3 * plane * sizeof(float), c->stream));
+        for (int k = 0; k < 3; ++k) g.Rl[k] = c->d_resid + k * plane;
         return SWE_OK;
     }
     return SWE_EINVAL;

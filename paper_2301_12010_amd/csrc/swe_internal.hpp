@@ -70,7 +70,8 @@ int stats_from_dev(const Geo &g, const DevScen &ds, swe_stats *st);
 struct Variant {
     int tx, ty, r, nt, waves;
     size_t lds_bytes;
-    void (*stage[3])(Geo, int, int);  // single-scenario stage kernels
+    void (*stage[3])(Geo, int, int);    // single-scenario stage kernels
+    void (*stage_c[3])(Geo, int, int);  // the same with the compensated level
 };
 // depth h = s - min(b, 0) of a stored-level plane into out (same pitch)
 int launch_depth(const Geo &g, const float *lev, float *out, hipStream_t stream);

@@ -68,6 +68,11 @@ struct Geo {
     // the surface to ~1e-7 m instead of an ulp of the depth (8e-6 m at 80 m),
     // and thin films on land keep their own precision.
     float *U[3], *A[3], *B[3];
+    // optional residual planes of the stored level of U, A and B (null when
+    // off): with them the level is kept as s + r, r the FP32 rounding error
+    // of s, and the RK combination adds with error-free sums, so increments
+    // below half an ulp of s are not lost (mass balance in shallow water)
+    float *Rl[3];
     const float *ghost;      // frozen FIXED ghosts (s, hu, hv, b), see ghost_index()
     DevScen *sd;
     double *mass_part;       // MASS_BLOCKS partial sums of the mass kernel
@@ -85,6 +90,14 @@ __device__ __forceinline__ int ghost_index(const Geo &G, int side, int field, in
 }
 
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Error-free sum (Knuth): s + e == a + b exactly, s = fl(a + b).
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
+{
+    s = a + b;
+    const float bv = s - a;
+    e = (a - (s - bv)) + (b - bv);
+}
 
 // Plane element access by a 32-bit element index.  A plane holds fewer than
 // 2^30 elements (checked at creation), so the byte offset fits 32 bits and the
@@ -494,7 +507,7 @@ __device__ __forceinline__ void tile_store(const Geo &G, int tx, int ty, const T
 // with the LDS tile still in use: the caller synchronises before overwriting
 // it.  PF: issue the combination's global reads before the y sweep (costs
 // 4R registers across it; off for variants whose register budget is tight).
-template <class C, bool PF>
+template <class C, bool PF, bool CMP>
 __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &sc, int tx, int ty, float *lds,
                                              StagePartials &acc)
 {
@@ -592,28 +605,68 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
         // the combination acts on the stored level: it differs from the depth
         // by a per-cell constant and the stage weights sum to one
         float os = fmaf(dt, Lh_, sv), ohu = fmaf(dt, Lhu_, hu), ohv = fmaf(dt, Lhv_, hv);
-        if (STAGE == 2) {
-            os = fmaf(0.75f, PF ? pun[k][0] : pld(G.U[0], gi), 0.25f * os);
-            ohu = fmaf(0.75f, PF ? pun[k][1] : pld(G.U[1], gi), 0.25f * ohu);
-            ohv = fmaf(0.75f, PF ? pun[k][2] : pld(G.U[2], gi), 0.25f * ohv);
+        float osl = 0.f;  // residual of the level (compensated kernels)
+        if (!CMP) {
+            if (STAGE == 2) {
+                os = fmaf(0.75f, PF ? pun[k][0] : pld(G.U[0], gi), 0.25f * os);
+                ohu = fmaf(0.75f, PF ? pun[k][1] : pld(G.U[1], gi), 0.25f * ohu);
+                ohv = fmaf(0.75f, PF ? pun[k][2] : pld(G.U[2], gi), 0.25f * ohv);
+            }
+            if (STAGE == 3) {
+                // u^n + (2/3)(w + dt L - u^n): the FP32 weights 1/3 and 2/3 sum
+                // to 1 + 3e-8, which would create mass every step; this form
+                // keeps the two weights summing to exactly one
+                const float un0 = PF ? pun[k][0] : pld(G.U[0], gi);
+                const float un1 = PF ? pun[k][1] : pld(G.U[1], gi);
+                const float un2 = PF ? pun[k][2] : pld(G.U[2], gi);
+                os = fmaf(2.f / 3.f, os - un0, un0);
+                ohu = fmaf(2.f / 3.f, ohu - un1, un1);
+                ohv = fmaf(2.f / 3.f, ohv - un2, un2);
+            }
+        } else {
+            // the same combination on (s, r) pairs with error-free sums and
+            // products; the value s + r is carried to ~2^-46 relative
+            const float slo = pld(STAGE == 1 ? G.Rl[0] : STAGE == 2 ? G.Rl[1] : G.Rl[2], gi);
+            float yh, yl;
+            two_sum(sv, fmaf(dt, Lh_, slo), yh, yl);
+            os = yh;
+            osl = yl;
+            if (STAGE == 2) {
+                const float uh = PF ? pun[k][0] : pld(G.U[0], gi), ul = pld(G.Rl[0], gi);
+                const float p1 = 0.75f * uh, e1 = fmaf(0.75f, uh, -p1);
+                float s2, e2;
+                two_sum(p1, 0.25f * yh, s2, e2);
+                const float l2 = ((e2 + e1) + 0.75f * ul) + 0.25f * yl;
+                os = s2 + l2;
+                osl = l2 - (os - s2);
+                ohu = fmaf(0.75f, PF ? pun[k][1] : pld(G.U[1], gi), 0.25f * ohu);
+                ohv = fmaf(0.75f, PF ? pun[k][2] : pld(G.U[2], gi), 0.25f * ohv);
+            }
+            if (STAGE == 3) {
+                const float uh = PF ? pun[k][0] : pld(G.U[0], gi), ul = pld(G.Rl[0], gi);
+                const float un1 = PF ? pun[k][1] : pld(G.U[1], gi);
+                const float un2 = PF ? pun[k][2] : pld(G.U[2], gi);
+                float dh, dl;
+                two_sum(yh, -uh, dh, dl);
+                dl += yl - ul;
+                const float p3 = (2.f / 3.f) * dh, e3 = fmaf(2.f / 3.f, dh, -p3);
+                float s3, e4;
+                two_sum(uh, p3, s3, e4);
+                const float l3 = ((e4 + e3) + (2.f / 3.f) * dl) + ul;
+                os = s3 + l3;
+                osl = l3 - (os - s3);
+                ohu = fmaf(2.f / 3.f, ohu - un1, un1);
+                ohv = fmaf(2.f / 3.f, ohv - un2, un2);
+            }
         }
-        if (STAGE == 3) {
-            // u^n + (2/3)(w + dt L - u^n): the FP32 weights 1/3 and 2/3 sum
-            // to 1 + 3e-8, which would create mass every step; this form
-            // keeps the two weights summing to exactly one
-            const float un0 = PF ? pun[k][0] : pld(G.U[0], gi);
-            const float un1 = PF ? pun[k][1] : pld(G.U[1], gi);
-            const float un2 = PF ? pun[k][2] : pld(G.U[2], gi);
-            os = fmaf(2.f / 3.f, os - un0, un0);
-            ohu = fmaf(2.f / 3.f, ohu - un1, un1);
-            ohv = fmaf(2.f / 3.f, ohv - un2, un2);
-        }
-        float oh = os - lo;
+        float oh = CMP ? (os - lo) + osl : os - lo;
         if (oh < 0.f) {
             acc.deficit -= oh;
             oh = 0.f;
             os = lo;
+            osl = 0.f;
         }
+        if (CMP) pst(STAGE == 1 ? G.Rl[1] : STAGE == 2 ? G.Rl[2] : G.Rl[0], gi, osl);
         const bool wet = oh > h_dry;
         if (!wet) {
             ohu = 0.f;
@@ -712,8 +765,8 @@ __device__ __forceinline__ void stage_publish(const Geo &G, const StageScalars &
 }
 
 // The whole stage on one tile (one block, one tile).
-// PF as for tile_compute.
-template <class C, bool PF>
+// PF as for tile_compute; CMP: the compensated level (Geo::Rl set).
+template <class C, bool PF, bool CMP = false>
 __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *lds, const int STAGE)
 {
     const StageScalars sc = stage_scalars(G, STAGE);
@@ -728,7 +781,7 @@ __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *
     }
     __syncthreads();
     StagePartials acc;
-    tile_compute<C, PF>(G, sc, tx, ty, lds, acc);
+    tile_compute<C, PF, CMP>(G, sc, tx, ty, lds, acc);
     stage_publish<C>(G, sc, acc, tx == 0 && ty == 0, lds);
 }
 
@@ -741,13 +794,13 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return x * q + (x < r ? x : r) + l;
 }
 
-// The stage kernel: one tile per block.
-template <class C, int S, int W>
+// The stage kernel: one tile per block.  CMP selects the compensated level.
+template <class C, int S, int W, bool CMP = false>
 __global__ __launch_bounds__(C::NT, W) void k_stage(Geo G, int ntx, int nblocks)
 {
     __shared__ float lds[C::LDS_FLOATS];
     const int id = xcd_remap(blockIdx.x, nblocks);
-    stage_tile<C, (W <= 2)>(G, id % ntx, id / ntx, lds, S);
+    stage_tile<C, (W <= 2), CMP>(G, id % ntx, id / ntx, lds, S);
 }
 
 }  // namespace swe

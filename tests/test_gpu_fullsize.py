@@ -186,7 +186,10 @@ def test_uneven_batch_over_the_full_run():
     # format (storing the depth everywhere drifts as much); it shrinks
     # twentyfold when the surface in the Lax-Friedrichs mass term is offset by
     # a constant (exact in exact arithmetic) and when the Manning friction is
-    # switched off, so it is an FP32 effect of thin films near the front
-    # whose exact cause is open.  Bound 1e-9 per step.
+    # switched off: still films near the front register sub-ulp
+    # Lax-Friedrichs exchanges that their coarsely stored wet neighbours
+    # round away.  The batch runs the plain level (the compensated level,
+    # an option of single contexts, keeps it near 1e-13).  Bound 1e-9 per
+    # step.
     worst = abs(drift[order[0]])
     assert worst <= 1e-9
