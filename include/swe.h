@@ -313,6 +313,30 @@ const char *swe_strerror(int code);
 /* Bytes of device memory one nx-by-ny scenario occupies. */
 size_t swe_footprint(int32_t nx, int32_t ny);
 
+/* Caller allocator for the library's device memory, so that a framework's
+ * caching allocator (torch's, for one) owns and accounts for it (plumbing,
+ * not an operation of the method).  It covers every device allocation:
+ * contexts (state, outputs, maximum-depth map, compensated planes), batches
+ * (scenarios, schedule tables) and servers (arena, schedule tables).  Pinned
+ * host memory for snapshots is not routed.
+ *   alloc(bytes, device, user) returns device memory of at least `bytes` on
+ *     HIP device `device`, aligned to 256 bytes, or NULL (the library call
+ *     then fails with SWE_ENOMEM; misaligned memory is handed back and the
+ *     call fails with SWE_EINVAL).
+ *   release(ptr, device, user) takes back what alloc returned.  The library
+ *     waits for the device to finish all work before it calls release, so
+ *     the allocator may reuse the memory at once.
+ * Both NULL restores hipMalloc/hipFree (the default); exactly one NULL is
+ * SWE_EINVAL.  Process-wide and thread-safe; it applies to allocations made
+ * after the call, and each allocation is released through the allocator that
+ * made it, even after another one is set, so the callbacks and `user` must
+ * stay valid until that memory is freed.  The callbacks run on the thread
+ * that called into the library, or on a server's own thread (its schedule
+ * tables), and must not call back into it. */
+typedef void *(*swe_alloc_fn)(size_t bytes, int32_t device, void *user);
+typedef void (*swe_release_fn)(void *ptr, int32_t device, void *user);
+int swe_set_allocator(swe_alloc_fn alloc, swe_release_fn release, void *user);
+
 #ifdef __cplusplus
 }
 #endif

@@ -168,7 +168,7 @@ static size_t al(size_t x) { return (x + 255) / 256 * 256; }
 SegmentLauncher::~SegmentLauncher()
 {
     if (graph) (void)hipGraphExecDestroy(graph);
-    if (dmem) (void)hipFree(dmem);
+    dev_free(dmem);
 }
 
 int SegmentLauncher::run(const std::vector<Geo> &geos, const std::vector<int> &ksteps, int vi, int mode,
@@ -202,13 +202,11 @@ int SegmentLauncher::run(const std::vector<Geo> &geos, const std::vector<int> &k
         graph = nullptr;
     }
     if (need > dbytes) {
-        if (dmem) (void)hipFree(dmem);
+        dev_free(dmem);
         dmem = nullptr;
         dbytes = 0;
-        if (hipMalloc(&dmem, need) != hipSuccess) {
-            (void)hipGetLastError();
-            return SWE_ENOMEM;
-        }
+        const int arc = dev_alloc(&dmem, need);
+        if (arc) return arc;
         dbytes = need;
     }
     if (cus <= 0) {
@@ -406,18 +404,15 @@ int swe_batch_track_max_depth(swe_batch *bt, int32_t index, int32_t enable)
     BatchScen &s = bt->sc[index];
     if (s.hmax) {
         SWE_HIP_TRY(hipStreamSynchronize(bt->stream));
-        (void)hipFree(s.hmax);
+        dev_free(s.hmax);
         s.hmax = nullptr;
         s.d.geo.hmax = nullptr;
     }
     if (!enable) return SWE_OK;
     const Geo &g = s.d.geo;
     const size_t bytes = (size_t)g.pitch * g.ny * sizeof(float);
-    if (hipMalloc(&s.hmax, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        s.hmax = nullptr;
-        return SWE_ENOMEM;
-    }
+    const int arc = dev_alloc((void **)&s.hmax, bytes);
+    if (arc) return arc;
     // start from the current depth, after the work already enqueued
     const int drc = launch_depth(g, g.U[0], s.hmax, bt->stream);
     if (drc) return drc;
@@ -443,7 +438,7 @@ void swe_batch_destroy(swe_batch *bt)
     if (!bt) return;
     if (bt->stream) (void)hipStreamSynchronize(bt->stream);
     for (auto &s : bt->sc) {
-        if (s.hmax) (void)hipFree(s.hmax);
+        dev_free(s.hmax);
         scenario_free(s.d);
     }
     if (bt->own_stream && bt->stream) (void)hipStreamDestroy(bt->stream);

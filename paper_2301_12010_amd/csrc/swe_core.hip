@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <unordered_map>
 #include <vector>
 
 #include "swe_internal.hpp"
@@ -413,17 +415,97 @@ int scenario_upload_into(void *mem, const swe_params &p, const HostFields &f, hi
     return SWE_OK;
 }
 
+// ---- device allocations ---------------------------------------------------
+namespace {
+struct AllocHook {
+    swe_alloc_fn alloc = nullptr;
+    swe_release_fn release = nullptr;
+    void *user = nullptr;
+    int device = 0;
+};
+std::mutex g_alloc_mu;
+AllocHook g_hook;                              // guarded by g_alloc_mu
+std::unordered_map<void *, AllocHook> g_owned;  // caller-allocated blocks, with their allocator
+}  // namespace
+
+int dev_alloc(void **p, size_t bytes)
+{
+    *p = nullptr;
+    AllocHook h;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        h = g_hook;
+    }
+    if (!h.alloc) {
+        if (hipMalloc(p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            return SWE_ENOMEM;
+        }
+        return SWE_OK;
+    }
+    if (hipGetDevice(&h.device) != hipSuccess) return SWE_EDEVICE;
+    void *m = h.alloc(bytes, h.device, h.user);
+    if (!m) return SWE_ENOMEM;
+    if (reinterpret_cast<uintptr_t>(m) % 256 != 0) {
+        h.release(m, h.device, h.user);
+        return SWE_EINVAL;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        g_owned[m] = h;
+    }
+    *p = m;
+    return SWE_OK;
+}
+
+void dev_free(void *p)
+{
+    if (!p) return;
+    AllocHook h;
+    bool caller = false;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        auto it = g_owned.find(p);
+        if (it != g_owned.end()) {
+            h = it->second;
+            caller = true;
+            g_owned.erase(it);
+        }
+    }
+    if (!caller) {
+        (void)hipFree(p);  // waits for the device itself
+        return;
+    }
+    // the allocator may hand the block out again at once: no kernel or copy
+    // of this library may still be using it
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != h.device) (void)hipSetDevice(h.device);
+    (void)hipDeviceSynchronize();
+    if (cur != h.device) (void)hipSetDevice(cur);
+    h.release(p, h.device, h.user);
+}
+
+static int set_alloc_hook(swe_alloc_fn a, swe_release_fn r, void *user)
+{
+    if (!a != !r) return SWE_EINVAL;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_hook.alloc = a;
+    g_hook.release = r;
+    g_hook.user = a ? user : nullptr;
+    return SWE_OK;
+}
+
 int scenario_upload(const swe_params &p, const HostFields &f, hipStream_t stream, DevScenario &d)
 {
     void *mem = nullptr;
     const size_t bytes = scenario_bytes(p.nx, p.ny);
-    if (hipMalloc(&mem, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return SWE_ENOMEM;
-    }
+    const int arc = dev_alloc(&mem, bytes);
+    if (arc) return arc;
     const int rc = scenario_upload_into(mem, p, f, stream, d);
     if (rc) {
-        (void)hipFree(mem);
+        dev_free(mem);
         d.base = nullptr;
     }
     return rc;
@@ -431,7 +513,7 @@ int scenario_upload(const swe_params &p, const HostFields &f, hipStream_t stream
 
 void scenario_free(DevScenario &d)
 {
-    if (d.base) (void)hipFree(d.base);
+    dev_free(d.base);
     d.base = nullptr;
 }
 
@@ -565,9 +647,9 @@ static void outputs_free(swe_ctx *c)
         if (o.h_meta[b]) (void)hipHostFree(o.h_meta[b]);
     }
     if (o.h_data) (void)hipHostFree(o.h_data);
-    if (o.d_slots) (void)hipFree(o.d_slots);
-    if (o.d_meta) (void)hipFree(o.d_meta);
-    if (o.d_times) (void)hipFree(o.d_times);
+    dev_free(o.d_slots);
+    dev_free(o.d_meta);
+    dev_free(o.d_times);
     o = OutputSet();
 }
 
@@ -738,8 +820,8 @@ void swe_destroy(swe_ctx *c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graph(c);
     outputs_free(c);
-    if (c->d_hmax) (void)hipFree(c->d_hmax);
-    if (c->d_resid) (void)hipFree(c->d_resid);
+    dev_free(c->d_hmax);
+    dev_free(c->d_resid);
     if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
     scenario_free(c->d);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -766,9 +848,9 @@ int swe_set_outputs(swe_ctx *c, const double *times, int32_t n)
     o.hdr.assign(n, SnapHeader{});
     o.ev_copy.assign(n, nullptr);
     o.queued.assign(n, 0);
-    if (hipMalloc(&o.d_times, n * sizeof(double)) != hipSuccess ||
-        hipMalloc(&o.d_meta, snap_meta_bytes(n)) != hipSuccess ||
-        hipMalloc(&o.d_slots, (size_t)n * 3 * plane * sizeof(float)) != hipSuccess ||
+    if (dev_alloc((void **)&o.d_times, n * sizeof(double)) != SWE_OK ||
+        dev_alloc((void **)&o.d_meta, snap_meta_bytes(n)) != SWE_OK ||
+        dev_alloc((void **)&o.d_slots, (size_t)n * 3 * plane * sizeof(float)) != SWE_OK ||
         hipHostMalloc(&o.h_data, (size_t)n * 3 * cells * sizeof(float), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&o.h_meta[0], snap_meta_bytes(n), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&o.h_meta[1], snap_meta_bytes(n), hipHostMallocDefault) != hipSuccess)
@@ -845,18 +927,15 @@ int swe_track_max_depth(swe_ctx *c, int32_t enable)
     drop_graph(c);  // captured steps carry the plane's address
     if (c->d_hmax) {
         SWE_HIP_TRY(hipStreamSynchronize(c->stream));
-        (void)hipFree(c->d_hmax);
+        dev_free(c->d_hmax);
         c->d_hmax = nullptr;
         c->d.geo.hmax = nullptr;
     }
     if (!enable) return SWE_OK;
     const Geo &g = c->d.geo;
     const size_t bytes = (size_t)g.pitch * g.ny * sizeof(float);
-    if (hipMalloc(&c->d_hmax, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        c->d_hmax = nullptr;
-        return SWE_ENOMEM;
-    }
+    const int arc = dev_alloc((void **)&c->d_hmax, bytes);
+    if (arc) return arc;
     // start from the current depth, after the work already enqueued
     const int drc = launch_depth(g, g.U[0], c->d_hmax, c->stream);
     if (drc) return drc;
@@ -895,17 +974,14 @@ int swe_set_option(swe_ctx *c, int32_t key, int64_t value)
         Geo &g = c->d.geo;
         if (c->d_resid) {
             SWE_HIP_TRY(hipStreamSynchronize(c->stream));
-            (void)hipFree(c->d_resid);
+            dev_free(c->d_resid);
             c->d_resid = nullptr;
             for (int k = 0; k < 3; ++k) g.Rl[k] = nullptr;
         }
         if (!value) return SWE_OK;
         const size_t plane = (size_t)g.pitch * g.ny;
-        if (hipMalloc(&c->d_resid, 3 * plane * sizeof(float)) != hipSuccess) {
-            (void)hipGetLastError();
-            c->d_resid = nullptr;
-            return SWE_ENOMEM;
-        }
+        const int arc = dev_alloc((void **)&c->d_resid, 3 * plane * sizeof(float));
+        if (arc) return arc;
         // the stored FP32 level is exact as it stands: residuals start at 0
         SWE_HIP_TRY(hipMemsetAsync(c->d_resid, 0, 3 * plane * sizeof(float), c->stream));
         for (int k = 0; k < 3; ++k) g.Rl[k] = c->d_resid + k * plane;
@@ -980,6 +1056,11 @@ size_t swe_footprint(int32_t nx, int32_t ny)
 {
     if (nx < 1 || ny < 1) return 0;
     return scenario_bytes(nx, ny);
+}
+
+int swe_set_allocator(swe_alloc_fn alloc, swe_release_fn release, void *user)
+{
+    return swe::set_alloc_hook(alloc, release, user);
 }
 
 const char *swe_strerror(int code)

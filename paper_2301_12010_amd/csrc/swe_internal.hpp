@@ -27,6 +27,13 @@ struct HostFields {
 
 int validate_params(const swe_params *p);
 
+// Device memory of the library: hipMalloc, or the caller's allocator when
+// swe_set_allocator has set one.  dev_alloc returns SWE_OK, SWE_ENOMEM or
+// SWE_EINVAL (memory not aligned to 256 bytes); dev_free (NULL-safe) hands
+// memory back to the allocator that made it, after the device is idle.
+int dev_alloc(void **p, size_t bytes);
+void dev_free(void *p);
+
 // Copies the five fields (host or device pointers) and validates them.
 int load_fields(const swe_params *p, const float *b, const float *n, const float *h,
                 const float *hu, const float *hv, HostFields &out);
@@ -48,7 +55,7 @@ struct DevScenario {
 
 size_t scenario_bytes(int nx, int ny);
 
-// Allocates (hipMalloc) and uploads on `stream`, then runs the init kernel.
+// Allocates (dev_alloc) and uploads on `stream`, then runs the init kernel.
 int scenario_upload(const swe_params &p, const HostFields &f, hipStream_t stream, DevScenario &d);
 // Uploads into caller-provided device memory of scenario_bytes() size.
 int scenario_upload_into(void *mem, const swe_params &p, const HostFields &f, hipStream_t stream,

@@ -3,7 +3,7 @@
 // A host thread owns a device arena of the memory budget.  Requests wait in a
 // FIFO queue; a request is admitted when a slot is free and its footprint
 // (swe_footprint) fits a first-fit hole of the arena, so admission is by HBM
-// footprint and never calls hipMalloc or hipFree.  Resident scenarios advance
+// footprint and allocates no device memory after create.  Resident scenarios advance
 // together in segments: one launch sequence advances every resident scenario
 // by min(segment_steps, its remaining steps).  While a segment runs, the
 // thread prepares and uploads newly admitted requests on a copy stream and
@@ -38,17 +38,14 @@ class Arena {
     int init(size_t bytes)
     {
         bytes_ = bytes / 256 * 256;
-        if (hipMalloc(&base_, bytes_) != hipSuccess) {
-            (void)hipGetLastError();
-            base_ = nullptr;
-            return SWE_ENOMEM;
-        }
+        const int rc = dev_alloc(&base_, bytes_);
+        if (rc) return rc;
         free_[0] = bytes_;
         return SWE_OK;
     }
     ~Arena()
     {
-        if (base_) (void)hipFree(base_);
+        dev_free(base_);
     }
     void *alloc(size_t n)
     {

@@ -76,6 +76,8 @@ class ServerStats(ctypes.Structure):
 # against include/swe.h)
 _VP = ctypes.c_void_p
 _FP = ctypes.c_void_p  # float* (host or device address)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p)
 _SIGS = {
     "swe_create": (ctypes.c_int, [ctypes.POINTER(Params), _FP, _FP, _FP, _FP, _FP, _VP, ctypes.POINTER(_VP)]),
     "swe_step": (ctypes.c_int, [_VP, ctypes.c_int32]),
@@ -118,6 +120,7 @@ _SIGS = {
     "swe_server_destroy": (None, [_VP]),
     "swe_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "swe_footprint": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "swe_set_allocator": (ctypes.c_int, [ALLOC_FN, RELEASE_FN, _VP]),
 }
 
 _LIB = None
@@ -319,6 +322,47 @@ def autotune(nx: int, ny: int, cache_path: str | None = None):
 
 def footprint(nx: int, ny: int) -> int:
     return int(_lib().swe_footprint(int(nx), int(ny)))
+
+
+# Every callback pair ever handed to the library: memory keeps the allocator
+# that made it, so a replaced pair may still be called to release it.
+_ALLOCATORS = []
+
+
+def set_allocator(alloc=None, release=None):
+    """Route the library's device allocations through ``alloc(nbytes, device)
+    -> address`` and ``release(address, device)`` (swe_set_allocator); both
+    None restores hipMalloc/hipFree.  An exception in ``alloc`` reads as out
+    of memory."""
+    if alloc is None and release is None:
+        _check(_lib().swe_set_allocator(ALLOC_FN(), RELEASE_FN(), None), "swe_set_allocator")
+        return
+
+    def _alloc(nbytes, device, _user):
+        try:
+            return int(alloc(int(nbytes), int(device))) or None
+        except Exception:
+            return None
+
+    def _release(ptr, device, _user):
+        release(int(ptr), int(device))
+
+    pair = (ALLOC_FN(_alloc) if alloc is not None else ALLOC_FN(),
+            RELEASE_FN(_release) if release is not None else RELEASE_FN())
+    _ALLOCATORS.append(pair)
+    _check(_lib().swe_set_allocator(pair[0], pair[1], None), "swe_set_allocator")
+
+
+def use_torch_allocator(enable: bool = True):
+    """Allocate the library's device memory from torch's caching allocator
+    (counted by torch.cuda.memory_allocated), or go back to hipMalloc."""
+    if not enable:
+        set_allocator(None, None)
+        return
+    import torch
+
+    set_allocator(lambda n, dev: torch.cuda.caching_allocator_alloc(n, dev),
+                  lambda p, dev: torch.cuda.caching_allocator_delete(p))
 
 
 class Batch:

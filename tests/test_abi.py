@@ -64,6 +64,13 @@ def test_host_only_calls():
     assert L.swe_read_max_depth(None, None) == swe.EINVAL
     assert L.swe_batch_track_max_depth(None, 0, 1) == swe.EINVAL
     assert L.swe_batch_read_max_depth(None, 0, None) == swe.EINVAL
+    # allocator hook: both callbacks or neither
+    assert L.swe_set_allocator(swe.ALLOC_FN(lambda n, d, u: None), swe.RELEASE_FN(), None) == swe.EINVAL
+    assert L.swe_set_allocator(swe.ALLOC_FN(), swe.RELEASE_FN(lambda p, d, u: None), None) == swe.EINVAL
+    assert L.swe_set_allocator(swe.ALLOC_FN(), swe.RELEASE_FN(), None) == swe.OK
+    with pytest.raises(swe.SweError):
+        swe.set_allocator(lambda n, d: 0, None)
+    swe.set_allocator(None, None)
 
 
 def test_create_rejects_bad_sizes_before_reading_fields():
