@@ -82,6 +82,8 @@ def _declare(L):
     L.oracle_destroy.argtypes = [P]
     L.oracle_num_threads.restype = ctypes.c_int
     L.oracle_num_threads.argtypes = []
+    L.oracle_set_friction.restype = None
+    L.oracle_set_friction.argtypes = [P, ctypes.c_int]
 
 
 def _dp(a: np.ndarray):
@@ -133,6 +135,10 @@ class Oracle:
 
     def step(self, nsteps: int) -> int:
         return int(self._L.oracle_step(self._ptr, int(nsteps)))
+
+    def set_friction(self, implicit: bool):
+        """Point-implicit friction per stage (reading R10) or the explicit term."""
+        self._L.oracle_set_friction(self._ptr, 1 if implicit else 0)
 
     def state(self):
         h = np.empty((self.ny, self.nx))

@@ -46,6 +46,14 @@
  *   R9  Boundaries: REFLECT mirrors three ghost layers (normal momentum odd);
  *       FIXED freezes the ghost (h, hu, hv) at the create-time values of the
  *       nearest interior cell and extends b linearly.
+ *   R10 Variant, off by default (oracle_set_friction): point-implicit
+ *       friction.  The paper keeps friction explicit and names an implicit
+ *       treatment as the alternative it did not take (Methods); this reading
+ *       takes each stage's friction term backward in time with kappa frozen
+ *       at the stage input w and not capped:
+ *         q_out = [a_n q^n + a_w (q_w + dt L'(w))] / (1 + a_w dt kappa(w)),
+ *       L' the right-hand side without friction, (a_n, a_w) = (0, 1),
+ *       (3/4, 1/4), (1/3, 2/3) for the three stages.
  *
  * Build: gcc -O2 -std=c11 -fopenmp -ffp-contract=off -fPIC -shared.
  */
@@ -81,8 +89,10 @@ typedef struct {
     double *bedx, *bedy;          /* interior bed terms */
     double *ghost[4][3];          /* frozen FIXED ghosts: [side][field][layer*len + k] */
     double t, mass, clamp_mass, runup, alpha_x, alpha_y, dt_last;
+    double *kap;                  /* interior friction rate of the stage input (implicit mode) */
     int64_t step;
     int nonfinite;
+    int friction_implicit;        /* R10 */
 } oracle_ctx;
 
 static inline size_t IX(const oracle_ctx *c, int i, int j)
@@ -406,7 +416,8 @@ static void rhs(oracle_ctx *c, const double *h, const double *hu, const double *
     }
 
     /* sources and assembly: L = ((-dF/dx) + (-dG/dy)) + S */
-    const double cap = (c->p.kappa_cap > 0.0 && dt > 0.0) ? c->p.kappa_cap / dt : INFINITY;
+    const int implicit = c->friction_implicit;
+    const double cap = (!implicit && c->p.kappa_cap > 0.0 && dt > 0.0) ? c->p.kappa_cap / dt : INFINITY;
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; j++) {
         for (int i = 0; i < nx; i++) {
@@ -418,6 +429,9 @@ static void rhs(oracle_ctx *c, const double *h, const double *hu, const double *
                 if (kappa > cap)
                     kappa = cap;
             }
+            c->kap[o] = kappa;
+            if (implicit)
+                kappa = 0.0; /* R10: taken in the combination instead */
             c->Lh[o] = c->fx[0][o] + c->gy[0][o];
             c->Lhu[o] = (c->fx[1][o] + c->gy[1][o]) + (c->bedx[o] - kappa * hu[e]);
             c->Lhv[o] = (c->fx[2][o] + c->gy[2][o]) + (c->bedy[o] - kappa * hv[e]);
@@ -448,6 +462,11 @@ static void combine(oracle_ctx *c, double an, double aw, double weight, double d
                 nh = an * hn[e] + aw * nh;
                 nhu = an * hun[e] + aw * nhu;
                 nhv = an * hvn[e] + aw * nhv;
+            }
+            if (c->friction_implicit) {
+                const double den = 1.0 + aw * dt * c->kap[o];
+                nhu /= den;
+                nhv /= den;
             }
             if (nh < 0.0) {
                 added += -nh;
@@ -491,7 +510,7 @@ void oracle_destroy(oracle_ctx *c)
     double **arrs[] = {&c->b, &c->gn2, &c->h, &c->hu, &c->hv, &c->h1, &c->hu1, &c->hv1,
                        &c->h2, &c->hu2, &c->hv2, &c->Lh, &c->Lhu, &c->Lhv,
                        &c->fx[0], &c->fx[1], &c->fx[2], &c->gy[0], &c->gy[1], &c->gy[2],
-                       &c->bedx, &c->bedy};
+                       &c->bedx, &c->bedy, &c->kap};
     for (size_t k = 0; k < sizeof arrs / sizeof arrs[0]; k++)
         free(*arrs[k]);
     for (int s = 0; s < 4; s++)
@@ -535,7 +554,7 @@ oracle_ctx *oracle_create(const oracle_params *p, const double *b, const double 
             return NULL;
         }
     double **in[] = {&c->gn2, &c->Lh, &c->Lhu, &c->Lhv, &c->fx[0], &c->fx[1], &c->fx[2],
-                     &c->gy[0], &c->gy[1], &c->gy[2], &c->bedx, &c->bedy};
+                     &c->gy[0], &c->gy[1], &c->gy[2], &c->bedx, &c->bedy, &c->kap};
     for (size_t k = 0; k < sizeof in / sizeof in[0]; k++)
         if (!(*in[k] = calloc(N, sizeof(double)))) {
             oracle_destroy(c);
@@ -628,6 +647,13 @@ int oracle_step(oracle_ctx *c, int nsteps)
         wave_speeds(c, c->h, c->hu, c->hv, &c->alpha_x, &c->alpha_y);
     }
     return c->nonfinite ? -4 : 0;
+}
+
+/* R10: 1 selects point-implicit friction, 0 (default) the explicit term. */
+void oracle_set_friction(oracle_ctx *c, int implicit)
+{
+    if (c)
+        c->friction_implicit = implicit ? 1 : 0;
 }
 
 /* Copy the interior state (any pointer may be NULL). */

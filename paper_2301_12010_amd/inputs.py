@@ -172,6 +172,24 @@ def steady_slope(nx: int = 64, ny: int = 4, dx: float = 1.0, depth: float = 0.5,
                                                manning=manning))
 
 
+def friction_channel(nx: int = 801, ny: int = 3, dx: float = 10.0, depth: float = 0.05,
+                     q0: float = 0.05, manning: float = 0.1, dt_fixed: float = 0.25,
+                     kappa_cap: float = 0.0, dtype=np.float32) -> Scenario:
+    """Uniform flow along x over a flat bed, slowed by Manning friction only.
+
+    West and east sides are frozen (FIXED) ghosts at the initial state, north
+    and south mirror ghosts; a fixed time step.  Away from the ends the flux
+    gradient vanishes, so the discharge follows the friction decay law.
+    """
+    z = np.zeros((ny, nx))
+    p = Params(nx, ny, dx, dx, cfl=0.0, dt_fixed=dt_fixed, kappa_cap=kappa_cap,
+               bc=(BC_FIXED, BC_FIXED, BC_REFLECT, BC_REFLECT))
+    f = lambda a: _f32(a, dtype)
+    return Scenario("friction_channel", p, f(z), f(np.full((ny, nx), manning)),
+                    f(np.full((ny, nx), depth)), f(np.full((ny, nx), q0)), f(z), 0,
+                    dict(depth=depth, q0=q0, manning=manning))
+
+
 def lake_at_rest(nx: int = 48, ny: int = 40, dx: float = 1.0, dy: float | None = None,
                  eta0: float = 1.7, seed: int = 7, nbumps: int = 6,
                  depth: float = 1.0, manning: float = 0.0, cfl: float = 0.4,

@@ -89,3 +89,12 @@ def bowl_u(t: float, h0: float, a: float, amp: float, g: float = G) -> float:
 def manning_q(depth: float, slope: float, n: float) -> float:
     """Uniform unit discharge q = sqrt(slope)/n depth^(5/3) (Section 2.3)."""
     return float(np.sqrt(slope) / n * depth ** (5.0 / 3.0))
+
+
+def friction_decay_q(t, q0: float, depth: float, n: float, g: float = 9.81):
+    """Unit discharge of uniform flow over a flat bed slowed by Manning
+    friction alone (Methods, Eq. (3) with no flux gradient or bed slope):
+    dq/dt = -c q^2 with c = g n^2 / depth^(7/3) for q > 0, so
+    q(t) = q0 / (1 + c q0 t)."""
+    c = g * n * n / depth ** (7.0 / 3.0)
+    return q0 / (1.0 + c * q0 * np.asarray(t, dtype=float))

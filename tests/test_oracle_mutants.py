@@ -135,6 +135,20 @@ def step_weights_flags(L):
     return not (w[0] > 1 - 1e-10 and w[1] + w[2] < 1e-10)
 
 
+def decay_flags(L):
+    # implicit friction against the friction decay law (first order in dt)
+    errs = []
+    for dt in (0.125, 0.0625):
+        sc = inputs.friction_channel(dt_fixed=dt, dtype=F64)
+        o = oracle.Oracle.from_scenario(sc, L=L)
+        o.set_friction(True)
+        o.step(int(round(2.0 / dt)))
+        q = o.state()[1][1, sc.params.nx // 2]
+        exact = A.friction_decay_q(2.0, sc.meta["q0"], sc.meta["depth"], sc.meta["manning"])
+        errs.append(abs(q - exact) / exact)
+    return not (errs[1] < 0.035 and 1.8 < errs[0] / errs[1] < 2.2)
+
+
 MUTANTS = [
     # (id, anchor, replacement, detector)
     ("surface_viscosity_on_h", "U[0] = h + b;", "U[0] = h;", lake_flags),
@@ -169,6 +183,10 @@ MUTANTS = [
      "a[k] = d[k] / (eps + beta[k]);", step_weights_flags),
     ("alpha_y_uses_u", "const double sx = fabs(u) + cel, sy = fabs(v) + cel;",
      "const double sx = fabs(u) + cel, sy = fabs(u) + cel;", transpose_flags),
+    ("implicit_friction_stage_weight", "const double den = 1.0 + aw * dt * c->kap[o];",
+     "const double den = 1.0 + dt * c->kap[o];", decay_flags),
+    ("implicit_friction_counted_twice", "kappa = 0.0; /* R10: taken in the combination instead */",
+     "kappa = kappa; /* R10: taken in the combination instead */", decay_flags),
     ("bed_source_x_index", "dbh[k] = bhat[k + 1] - bhat[k];", "dbh[k] = bhat[k + 1] - bhat[k + 1];", lake_flags),
 ]
 

@@ -301,3 +301,78 @@ def test_invalid_inputs_rejected():
     small = inputs.dam_break(nx=2, ny=4)
     with pytest.raises(ValueError):
         oracle.Oracle.from_scenario(small)
+
+
+# ---------------------------------------------------------------------------
+# Point-implicit friction, the variant the paper declines (Methods; reading
+# R10 of the checker)
+# ---------------------------------------------------------------------------
+
+def decay_errors(L=None, dts=(0.25, 0.125, 0.0625), T=2.0):
+    """Relative error of the mid-channel discharge at time T against the
+    friction decay law, per time step; also checks h and the sign of q."""
+    errs = []
+    for dt in dts:
+        sc = inputs.friction_channel(dt_fixed=dt, dtype=F64)
+        o = oracle.Oracle.from_scenario(sc, L=L)
+        o.set_friction(True)
+        qs = []
+        for _ in range(int(round(T / dt))):
+            assert o.step(1) == 0
+            h, hu, hv = o.state()
+            qs.append(hu[1, sc.params.nx // 2])
+            assert h[1, sc.params.nx // 2] == sc.meta["depth"]
+        qs = np.array(qs)
+        assert np.all(qs > 0) and np.all(np.diff(qs) <= 0)
+        exact = A.friction_decay_q(T, sc.meta["q0"], sc.meta["depth"], sc.meta["manning"])
+        errs.append(abs(qs[-1] - exact) / exact)
+    return errs
+
+
+def test_implicit_friction_converges_to_the_decay_law():
+    # kappa dt = 1.3 to 0.33 at the start: first order in dt (each stage
+    # takes its friction backward in time with the rate of its input)
+    errs = decay_errors()
+    assert 1.8 < errs[0] / errs[1] < 2.2 and 1.8 < errs[1] / errs[2] < 2.2
+    assert errs[2] < 0.035
+
+
+def test_implicit_friction_is_stable_where_explicit_is_not():
+    # Manning n = 10 on a 5 cm film: kappa dt ~ 2.7e3 at the start
+    sc = inputs.friction_channel(manning=10.0, dt_fixed=0.5, dtype=F64)
+    mid = sc.params.nx // 2
+    o = oracle.Oracle.from_scenario(sc)
+    o.set_friction(True)
+    qs = []
+    for _ in range(8):
+        assert o.step(1) == 0
+        qs.append(o.state()[1][1, mid])
+    assert np.all(np.diff([sc.meta["q0"]] + qs) < 0) and min(qs) > 0
+    e = oracle.Oracle.from_scenario(sc)  # explicit, no stiffness cap
+    rc = e.step(3)
+    q = e.state()[1][1, mid]
+    assert rc != 0 or not np.isfinite(q) or q < 0 or q > sc.meta["q0"]
+
+
+def test_implicit_friction_keeps_the_steady_slope():
+    # the Manning discharge balances the bed slope; taking the friction
+    # implicitly leaves that exact discrete steady state in place
+    sc = inputs.steady_slope(dtype=F64)
+    o = oracle.Oracle.from_scenario(sc)
+    o.set_friction(True)
+    o.step(50)
+    h, hu, hv = o.state()
+    assert np.abs(h - sc.h).max() < 1e-12
+    assert np.abs(hu - sc.hu).max() < 1e-11
+    assert np.abs(hv).max() == 0.0
+
+
+def test_implicit_friction_without_manning_is_the_explicit_scheme():
+    sc = inputs.random_wet(24, 18, seed=4, dry_fraction=0.1, manning=0.0)
+    a = oracle.Oracle.from_scenario(sc)
+    b = oracle.Oracle.from_scenario(sc)
+    b.set_friction(True)
+    a.step(6)
+    b.step(6)
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
