@@ -122,6 +122,17 @@ void swe_destroy(swe_ctx *ctx);
  * the planes cannot be allocated (the option is then off).  Contexts only:
  * batches and servers run without it. */
 #define SWE_OPT_COMPENSATED 3
+/* 1: point-implicit Manning friction (Methods: the paper keeps friction
+ * explicit and names an implicit treatment as the alternative it declines).
+ * Each RK stage takes its own friction term backward in time with the rate
+ * kappa = g n^2 |q| / h^(7/3) of the stage input, uncapped (kappa_cap is
+ * ignored): q_out = [a_n q^n + a_w (q + dt L')] / (1 + a_w dt kappa), L' the
+ * right-hand side without friction, (a_n, a_w) = (0, 1), (3/4, 1/4),
+ * (1/3, 2/3).  Stable for any friction stiffness; first order in dt where the
+ * friction dominates.  0 (default): the explicit term of the paper.  Can be
+ * switched at any time (the captured graph is dropped); other values are
+ * SWE_EINVAL.  Contexts only: batches and servers use the explicit term. */
+#define SWE_OPT_FRICTION_IMPLICIT 4
 int swe_set_option(swe_ctx *ctx, int32_t key, int64_t value);
 
 /* Device addresses of the context's live state (depth h, hu, hv of u^n) and

@@ -208,24 +208,9 @@ static int launch_snap(const Geo &g, const double *times, SnapMeta *m, float *sl
 // ---------------------------------------------------------------------------
 // tile variants
 // ---------------------------------------------------------------------------
-// (tile width, tile height, cells per thread per sweep, minimum waves per SIMD)
-#define SWE_TILE_LIST(X) \
-    X(64, 16, 8, 2)      \
-    X(64, 32, 8, 2)      \
-    X(32, 32, 8, 2)      \
-    X(64, 16, 4, 2)      \
-    X(128, 16, 8, 2)     \
-    X(64, 16, 4, 3)      \
-    X(32, 32, 4, 3)      \
-    X(32, 16, 2, 2)      \
-    X(16, 16, 2, 2)      \
-    X(16, 16, 1, 2)
-
 #define SWE_VARIANT(TX, TY, R, W)                                                                    \
     {TX, TY, R, TileCfg<TX, TY, R>::NT, W, sizeof(float) * TileCfg<TX, TY, R>::LDS_FLOATS,          \
-     {k_stage<TileCfg<TX, TY, R>, 1, W>, k_stage<TileCfg<TX, TY, R>, 2, W>, k_stage<TileCfg<TX, TY, R>, 3, W>}, \
-     {k_stage<TileCfg<TX, TY, R>, 1, W, true>, k_stage<TileCfg<TX, TY, R>, 2, W, true>,                 \
-      k_stage<TileCfg<TX, TY, R>, 3, W, true>}},
+     {k_stage<TileCfg<TX, TY, R>, 1, W>, k_stage<TileCfg<TX, TY, R>, 2, W>, k_stage<TileCfg<TX, TY, R>, 3, W>}},
 
 static const Variant g_variants[] = {SWE_TILE_LIST(SWE_VARIANT)};
 
@@ -236,8 +221,13 @@ int launch_stage(const Variant &v, int stage, const Geo &g, hipStream_t stream)
 {
     const int ntx = (g.nx + v.tx - 1) / v.tx, nty = (g.ny + v.ty - 1) / v.ty;
     const int nb = ntx * nty;
-    hipLaunchKernelGGL(g.Rl[0] ? v.stage_c[stage - 1] : v.stage[stage - 1], dim3(nb), dim3(v.nt), 0, stream, g, ntx,
-                       nb);
+    const int mode = (g.Rl[0] ? 1 : 0) + (g.fric_implicit ? 2 : 0);
+    const int vi = (int)(&v - g_variants);
+    void (*k)(Geo, int, int) = v.stage[stage - 1];
+    if (mode == 1) k = g_stage_mode1[vi].k[stage - 1];
+    if (mode == 2) k = g_stage_mode2[vi].k[stage - 1];
+    if (mode == 3) k = g_stage_mode3[vi].k[stage - 1];
+    hipLaunchKernelGGL(k, dim3(nb), dim3(v.nt), 0, stream, g, ntx, nb);
     return hipGetLastError() == hipSuccess ? SWE_OK : SWE_EDEVICE;
 }
 
@@ -373,6 +363,7 @@ int scenario_upload_into(void *mem, const swe_params &p, const HostFields &f, hi
     g.h_dry = (float)p.h_dry;
     g.eps16 = (float)(16.0 * p.weno_eps);
     g.kappa_cap = (float)p.kappa_cap;
+    g.fric_implicit = 0;
     g.cfl = (float)p.cfl;
     g.dt_fixed = (float)p.dt_fixed;
     float *planes[11];
@@ -966,6 +957,12 @@ int swe_set_option(swe_ctx *c, int32_t key, int64_t value)
         if (value < -1 || value >= variant_count()) return SWE_EINVAL;
         c->tile = (int)value;
         drop_graph(c);
+        return SWE_OK;
+    }
+    if (key == SWE_OPT_FRICTION_IMPLICIT) {
+        if (value != 0 && value != 1) return SWE_EINVAL;
+        drop_graph(c);  // captured steps carry the flag in their arguments
+        c->d.geo.fric_implicit = (int)value;
         return SWE_OK;
     }
     if (key == SWE_OPT_COMPENSATED) {

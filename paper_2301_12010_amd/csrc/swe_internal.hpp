@@ -78,8 +78,30 @@ struct Variant {
     int tx, ty, r, nt, waves;
     size_t lds_bytes;
     void (*stage[3])(Geo, int, int);    // single-scenario stage kernels
-    void (*stage_c[3])(Geo, int, int);  // the same with the compensated level
 };
+// (tile width, tile height, cells per thread per sweep, minimum waves per SIMD)
+#define SWE_TILE_LIST(X) \
+    X(64, 16, 8, 2)      \
+    X(64, 32, 8, 2)      \
+    X(32, 32, 8, 2)      \
+    X(64, 16, 4, 2)      \
+    X(128, 16, 8, 2)     \
+    X(64, 16, 4, 3)      \
+    X(32, 32, 4, 3)      \
+    X(32, 16, 2, 2)      \
+    X(16, 16, 2, 2)      \
+    X(16, 16, 1, 2)
+// Stage kernels of every tile variant (in SWE_TILE_LIST order) in the
+// optional modes of a context: 1 the compensated level, 2 point-implicit
+// friction, 3 both.  One translation unit per mode (swe_mode<N>.hip), so the
+// sets compile in parallel.
+struct StageSet {
+    void (*k[3])(Geo, int, int);
+};
+#define SWE_STAGE_SET(TX, TY, R, W, CMP, IMP)                                                       \
+    {{k_stage<TileCfg<TX, TY, R>, 1, W, CMP, IMP>, k_stage<TileCfg<TX, TY, R>, 2, W, CMP, IMP>,      \
+      k_stage<TileCfg<TX, TY, R>, 3, W, CMP, IMP>}},
+extern const StageSet g_stage_mode1[], g_stage_mode2[], g_stage_mode3[];
 // depth h = s - min(b, 0) of a stored-level plane into out (same pitch)
 int launch_depth(const Geo &g, const float *lev, float *out, hipStream_t stream);
 int variant_count();

@@ -60,7 +60,7 @@ struct Geo {
     float dx, dy, inv_dx, inv_dy;
     float g, half_g, h_dry, eps16;  // eps16 = 16 * weno_eps (the kernels' indicator scale)
     float kappa_cap, cfl, dt_fixed;
-    int pad;
+    int fric_implicit;       // 1: point-implicit friction (the host launches the IMP kernels)
     const float *b, *gn2;    // bed and g n^2 planes
     // u^n, u^(1), u^(2): planes of (s, hu, hv) where s = h + min(b, 0) is the
     // stored level: the surface elevation h + b where the bed lies below the
@@ -507,7 +507,11 @@ __device__ __forceinline__ void tile_store(const Geo &G, int tx, int ty, const T
 // with the LDS tile still in use: the caller synchronises before overwriting
 // it.  PF: issue the combination's global reads before the y sweep (costs
 // 4R registers across it; off for variants whose register budget is tight).
-template <class C, bool PF, bool CMP>
+// IMP: point-implicit friction.  Each stage takes its own friction term
+// backward in time with the rate kappa of its input, uncapped:
+// q_out = [a_n q^n + a_w (q + dt L')] / (1 + a_w dt kappa), L' without
+// friction, a_w = 1, 1/4, 2/3 (an option; the paper's friction is explicit).
+template <class C, bool PF, bool CMP, bool IMP>
 __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &sc, int tx, int ty, float *lds,
                                              StagePartials &acc)
 {
@@ -592,15 +596,21 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
         float Lhu_ = Xr[C::XPLANE + xi] + res[k][1];
         float Lhv_ = Xr[2 * C::XPLANE + xi] + res[k][2];
         // explicit Manning friction, wet cells only, rate capped at kappa_cap/dt
+        // (IMP: the uncapped rate, taken after the combination)
         const float gn2 = PF ? pgn2[k] : pld(G.gn2, gi);
+        float kimp = 0.f;
         if (h > h_dry && gn2 > 0.f) {
             // |q| as a sum of two rounded squares: the same for (hu, hv) and
             // (hv, hu), so the step commutes with exchanging x and y
             const float qn = sqrtf(hu * hu + hv * hv);
             const float hm73 = __builtin_amdgcn_exp2f(-2.33333333333333f * __builtin_amdgcn_logf(h));
-            const float kap = fminf(gn2 * qn * hm73, sc.kcap);
-            Lhu_ = fmaf(-kap, hu, Lhu_);
-            Lhv_ = fmaf(-kap, hv, Lhv_);
+            if (IMP) {
+                kimp = gn2 * qn * hm73;
+            } else {
+                const float kap = fminf(gn2 * qn * hm73, sc.kcap);
+                Lhu_ = fmaf(-kap, hu, Lhu_);
+                Lhv_ = fmaf(-kap, hv, Lhv_);
+            }
         }
         // the combination acts on the stored level: it differs from the depth
         // by a per-cell constant and the stage weights sum to one
@@ -658,6 +668,12 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
                 ohu = fmaf(2.f / 3.f, ohu - un1, un1);
                 ohv = fmaf(2.f / 3.f, ohv - un2, un2);
             }
+        }
+        if (IMP && kimp > 0.f) {
+            const float aw = STAGE == 1 ? 1.f : STAGE == 2 ? 0.25f : 2.f / 3.f;
+            const float rden = frcp(fmaf(aw * dt, kimp, 1.f));
+            ohu *= rden;
+            ohv *= rden;
         }
         float oh = CMP ? (os - lo) + osl : os - lo;
         if (oh < 0.f) {
@@ -765,8 +781,8 @@ __device__ __forceinline__ void stage_publish(const Geo &G, const StageScalars &
 }
 
 // The whole stage on one tile (one block, one tile).
-// PF as for tile_compute; CMP: the compensated level (Geo::Rl set).
-template <class C, bool PF, bool CMP = false>
+// PF and IMP as for tile_compute; CMP: the compensated level (Geo::Rl set).
+template <class C, bool PF, bool CMP = false, bool IMP = false>
 __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *lds, const int STAGE)
 {
     const StageScalars sc = stage_scalars(G, STAGE);
@@ -781,7 +797,7 @@ __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *
     }
     __syncthreads();
     StagePartials acc;
-    tile_compute<C, PF, CMP>(G, sc, tx, ty, lds, acc);
+    tile_compute<C, PF, CMP, IMP>(G, sc, tx, ty, lds, acc);
     stage_publish<C>(G, sc, acc, tx == 0 && ty == 0, lds);
 }
 
@@ -794,13 +810,14 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return x * q + (x < r ? x : r) + l;
 }
 
-// The stage kernel: one tile per block.  CMP selects the compensated level.
-template <class C, int S, int W, bool CMP = false>
+// The stage kernel: one tile per block.  CMP selects the compensated level,
+// IMP the point-implicit friction.
+template <class C, int S, int W, bool CMP = false, bool IMP = false>
 __global__ __launch_bounds__(C::NT, W) void k_stage(Geo G, int ntx, int nblocks)
 {
     __shared__ float lds[C::LDS_FLOATS];
     const int id = xcd_remap(blockIdx.x, nblocks);
-    stage_tile<C, (W <= 2), CMP>(G, id % ntx, id / ntx, lds, S);
+    stage_tile<C, (W <= 2), CMP, IMP>(G, id % ntx, id / ntx, lds, S);
 }
 
 }  // namespace swe

@@ -1,0 +1,149 @@
+"""GPU: point-implicit friction (SWE_OPT_FRICTION_IMPLICIT) against the FP64
+checker's implicit variant, element by element on the same seeded inputs.
+Also: without friction it is bitwise the explicit scheme, every tile variant
+gives the same state in every optional mode, and stiff films stay bounded."""
+import sys
+
+import numpy as np
+import pytest
+
+import analytic as A
+import oracle
+from parity import TOL_SHOCK, TOL_SMOOTH, field_errors, front_split_errors
+from paper_2301_12010_amd import inputs, swe
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_run(sc, nsteps, implicit=1, compensated=0, tile=None):
+    say(f"case {sc.name} {sc.params.nx}x{sc.params.ny} steps={nsteps} implicit={implicit} "
+        f"compensated={compensated} tile={tile}")
+    s = swe.Solver.from_scenario(sc)
+    s.set_option(swe.OPT_FRICTION_IMPLICIT, implicit)
+    s.set_option(swe.OPT_COMPENSATED, compensated)
+    if tile is not None:
+        s.set_option(swe.OPT_TILE, tile)
+    s.step(nsteps)
+    h, hu, hv, st = s.read()
+    s.close()
+    assert st["status"] == swe.OK
+    return (h, hu, hv), st
+
+
+def checker_run(sc, nsteps):
+    o = oracle.Oracle.from_scenario(sc)
+    o.set_friction(True)
+    assert o.step(nsteps) == 0
+    return o.state(), o.scalars()
+
+
+@pytest.mark.parametrize("nx,ny,dry", [(33, 17, 0.0), (130, 70, 0.0), (130, 70, 0.1)])
+def test_random_wet_matches_checker(nx, ny, dry):
+    sc = inputs.random_wet(nx, ny, seed=300 + nx + ny, dry_fraction=dry, manning=0.05)
+    for n in (1, 5):
+        g, st = gpu_run(sc, n)
+        r, rs = checker_run(sc, n)
+        e = field_errors(g, r)
+        say("errors", e)
+        assert max(e) <= (TOL_SMOOTH if dry == 0.0 else TOL_SHOCK), e
+        if dry == 0.0:
+            # with near-dry cells the wave speed hu/h, hence dt, carries the
+            # FP32 error of a depth taken as a difference of levels
+            assert abs(st["t"] - rs["t"]) <= 1e-6 * rs["t"]
+
+
+def test_friction_channel_follows_the_decay_law():
+    # kappa dt = 0.33 at the start; away from the frozen ends the discharge
+    # obeys dq/dt = -g n^2 q^2 / h^(7/3)
+    sc = inputs.friction_channel(dt_fixed=0.0625)
+    n = 32
+    g, st = gpu_run(sc, n)
+    r, rs = checker_run(sc, n)
+    e = field_errors(g, r)
+    mid = sc.params.nx // 2
+    exact = A.friction_decay_q(rs["t"], sc.meta["q0"], sc.meta["depth"], sc.meta["manning"])
+    say("errors", e, "q", g[1][1, mid], r[1][1, mid], exact)
+    assert max(e) <= TOL_SMOOTH, e
+    assert abs(g[1][1, mid] - exact) / exact < 0.035
+    # the frozen ends reach at most 9 cells per step into the channel
+    assert np.all(g[0][1, 9 * n + 1:sc.params.nx - 9 * n - 1] == np.float32(sc.meta["depth"]))
+
+
+def test_stiff_film_stays_bounded():
+    # Manning n = 10 on a 5 cm film, kappa dt ~ 2.7e3: the discharge decays
+    # monotonically and stays positive, as in the checker
+    sc = inputs.friction_channel(manning=10.0, dt_fixed=0.5)
+    mid = sc.params.nx // 2
+    s = swe.Solver.from_scenario(sc)
+    s.set_option(swe.OPT_FRICTION_IMPLICIT, 1)
+    o = oracle.Oracle.from_scenario(sc)
+    o.set_friction(True)
+    qs = [float(sc.meta["q0"])]
+    for _ in range(8):
+        s.step(1)
+        h, hu, hv, st = s.read()
+        assert st["status"] == swe.OK
+        assert o.step(1) == 0
+        q, qr = float(hu[1, mid]), o.state()[1][1, mid]
+        assert 0 < q < qs[-1]
+        assert abs(q - qr) <= 1e-4 * qr
+        qs.append(q)
+    s.close()
+
+
+def test_without_friction_equals_the_explicit_scheme_bitwise():
+    sc = inputs.random_wet(70, 45, seed=43, dry_fraction=0.1, manning=0.0)
+    a, _ = gpu_run(sc, 10, implicit=0)
+    b, _ = gpu_run(sc, 10, implicit=1)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_shallow_wet_dry_coast_with_both_options():
+    # 2 m deep beach scenario: implicit friction alone and together with the
+    # compensated level, against the checker's implicit variant
+    sc = inputs.uneven_scenario(2, inputs.uneven_plan())
+    r, _ = checker_run(sc, 50)
+    for comp in (0, 1):
+        g, st = gpu_run(sc, 50, implicit=1, compensated=comp)
+        e = front_split_errors(g, r)
+        say("errors", e)
+        assert max(e[:3]) <= TOL_SHOCK and e[3] <= 5e-3
+
+
+@pytest.mark.parametrize("implicit,compensated", [(0, 1), (1, 0), (1, 1)])
+def test_every_tile_variant_bitwise_identical_in_each_mode(implicit, compensated):
+    sc = inputs.random_wet(100, 37, seed=77, dry_fraction=0.1, manning=0.05)
+    ref = None
+    for tv in swe.tile_variants():
+        g, _ = gpu_run(sc, 4, implicit=implicit, compensated=compensated, tile=tv["index"])
+        if ref is None:
+            ref = g
+            continue
+        for x, y in zip(g, ref):
+            assert np.array_equal(x, y), tv
+
+
+def test_transposed_problem_gives_the_transposed_state():
+    sc = inputs.random_wet(70, 45, seed=41, dry_fraction=0.1, manning=0.05)
+    a, sa = gpu_run(sc, 15)
+    b, sb = gpu_run(inputs.transpose(sc), 15)
+    assert np.array_equal(b[0], a[0].T) and np.array_equal(b[1], a[2].T) and np.array_equal(b[2], a[1].T)
+    assert sa["t"] == sb["t"]
+
+
+def test_option_values():
+    s = swe.Solver.from_scenario(inputs.dam_break())
+    with pytest.raises(swe.SweError):
+        s.set_option(swe.OPT_FRICTION_IMPLICIT, 2)
+    s.set_option(swe.OPT_FRICTION_IMPLICIT, 1)
+    s.step(3)
+    s.set_option(swe.OPT_FRICTION_IMPLICIT, 0)
+    s.step(3)
+    assert s.read()[3]["step"] == 6
+    s.close()
