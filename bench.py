@@ -178,6 +178,8 @@ def run_large(args, torch, inputs, swe):
     s = swe.Solver.from_scenario(sc, stream=stream)
     s.set_option(swe.OPT_TILE, tile)
     s.set_option(swe.OPT_GRAPH_STEPS, args.graph_steps)
+    s.set_option(swe.OPT_COMPENSATED, int(args.compensated))
+    s.set_option(swe.OPT_FRICTION_IMPLICIT, int(args.friction_implicit))
     s.step(args.warmup)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
@@ -198,19 +200,23 @@ def run_large(args, torch, inputs, swe):
     kms = s.time_stages(20)
     avg_ms = sum(kms) / 3.0
     n = sc.cells
-    bytes_launch = n * sum(BYTES_STAGE) / 3.0
+    # the compensated level reads and writes its residual planes too
+    bytes_cell = (sum(BYTES_STAGE) + (8 + 12 + 12 if args.compensated else 0)) / 3.0
+    bytes_launch = n * bytes_cell
     flops_launch = n * FLOPS_STAGE
     ach_bw = bytes_launch / (avg_ms * 1e-3)
     ach_fl = flops_launch / (avg_ms * 1e-3)
     tv = swe.tile_variants()[tile]
-    traffic = measured_traffic(sc.name, (tv["tx"], tv["ty"], tv["r"]))
+    # counters were taken for the default kernels only
+    plain = not (args.compensated or args.friction_implicit)
+    traffic = measured_traffic(sc.name, (tv["tx"], tv["ty"], tv["r"])) if plain else None
     roof_alu = {"bound": "alu", "achieved": ach_fl / 1e12, "peak": FP32_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": ach_fl / FP32_PEAK, "traffic": traffic,
                 "kernel": "k_stage (3 stage launches per step)", "kernel_ms": kms,
                 "flops_per_cell_launch": FLOPS_STAGE}
     roof_hbm = {"bound": "hbm", "achieved": ach_bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": ach_bw / HBM_PEAK, "traffic": traffic,
-                "bytes_per_cell_launch": sum(BYTES_STAGE) / 3.0}
+                "bytes_per_cell_launch": bytes_cell}
     roofline = roof_alu if roof_alu["frac"] >= roof_hbm["frac"] else roof_hbm
     other = roof_hbm if roofline is roof_alu else roof_alu
     outputs = None if args.no_outputs else measure_outputs(s, torch, stream, sc)
@@ -549,6 +555,10 @@ def main():
                          "serving: Poisson serving at --serve-loads of capacity")
     ap.add_argument("--uneven-count", type=int, default=200)
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.7, 1.0])
+    ap.add_argument("--compensated", action="store_true",
+                    help="main line with the compensated level (SWE_OPT_COMPENSATED)")
+    ap.add_argument("--friction-implicit", action="store_true",
+                    help="main line with point-implicit friction (SWE_OPT_FRICTION_IMPLICIT)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -579,6 +589,9 @@ def main():
                    "tile": [tv["tx"], tv["ty"], tv["r"]], "graph_steps": args.graph_steps},
         "roofline": roofline, "roofline_other": other,
     }
+    if args.compensated or args.friction_implicit:
+        out["config"]["options"] = {"compensated": bool(args.compensated),
+                                    "friction": "implicit" if args.friction_implicit else "explicit"}
     if e2e is not None:
         out["end_to_end"] = e2e
     if outputs is not None:
