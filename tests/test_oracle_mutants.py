@@ -5,6 +5,7 @@ a wrong sign or index, a transposed operand, a wrong constant), compiled into
 a temporary directory on the CPU, and run against the pin that should notice.
 The unaltered checker passes the same pins in ``test_oracle_pins.py``.
 """
+import dataclasses
 import subprocess
 from pathlib import Path
 
@@ -149,6 +150,30 @@ def decay_flags(L):
     return not (errs[1] < 0.035 and 1.8 < errs[0] / errs[1] < 2.2)
 
 
+def dt_flags(L):
+    # uniform flow along x on anisotropic cells: dt from u + sqrt(g h) along
+    # x and sqrt(g h) along y
+    sc = inputs.friction_channel(nx=64, dtype=F64)
+    p = dataclasses.replace(sc.params, cfl=0.4, dt_fixed=0.0, dx=10.0, dy=25.0)
+    o = oracle.Oracle(p, *sc.fields(), L=L)
+    o.step(1)
+    c = np.sqrt(9.81 * sc.meta["depth"])
+    expect = 0.4 / ((sc.meta["q0"] / sc.meta["depth"] + c) / 10.0 + c / 25.0)
+    return not abs(o.scalars()["dt"] - expect) <= 1e-14 * expect
+
+
+def runup_flags(L):
+    # a still lake against a planar beach: the highest bed under water
+    nx = 60
+    X = (np.arange(nx) + 0.5)
+    b = np.tile(0.05 * (X - 30.0), (5, 1))
+    h = np.maximum(0.3 - b, 0.0)
+    z = np.zeros_like(b)
+    o = oracle.Oracle(inputs.Params(nx, 5, 1.0, 1.0), b, z, h, z, z, L=L)
+    m = (b > 0) & (h > 1e-3)
+    return o.scalars()["runup"] != b[m].max()
+
+
 MUTANTS = [
     # (id, anchor, replacement, detector)
     ("surface_viscosity_on_h", "U[0] = h + b;", "U[0] = h;", lake_flags),
@@ -187,6 +212,10 @@ MUTANTS = [
      "const double den = 1.0 + dt * c->kap[o];", decay_flags),
     ("implicit_friction_counted_twice", "kappa = 0.0; /* R10: taken in the combination instead */",
      "kappa = kappa; /* R10: taken in the combination instead */", decay_flags),
+    ("dt_cell_sizes_swapped", "const double den = ax / c->p.dx + ay / c->p.dy;",
+     "const double den = ax / c->p.dy + ay / c->p.dx;", dt_flags),
+    ("runup_counts_dry_beach", "if (c->b[e] > 0.0 && c->h[e] > c->p.h_dry && c->b[e] > r)",
+     "if (c->b[e] > 0.0 && c->b[e] > r)", runup_flags),
     ("bed_source_x_index", "dbh[k] = bhat[k + 1] - bhat[k];", "dbh[k] = bhat[k + 1] - bhat[k + 1];", lake_flags),
 ]
 

@@ -5,6 +5,8 @@ formulas: they compare it with closed forms (Stoker dam break, Thacker bowl,
 Manning uniform flow, lake at rest), polynomial exactness of the WENO5
 reconstruction, conservation, and exact symmetries of the discrete operator.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -376,3 +378,60 @@ def test_implicit_friction_without_manning_is_the_explicit_scheme():
     b.step(6)
     for x, y in zip(a.state(), b.state()):
         assert np.array_equal(x, y)
+
+
+# ---------------------------------------------------------------------------
+# Time step and runup diagnostics (Methods, Eq. (7) and the Lax-Friedrichs
+# paragraph: global wave speeds; Section 2.4: runup)
+# ---------------------------------------------------------------------------
+
+def dt_of_first_step(params, fields):
+    o = oracle.Oracle(params, *fields)
+    assert o.step(1) == 0
+    return o.scalars()["dt"]
+
+
+def test_time_step_of_still_water_is_the_gravity_wave_limit():
+    # still water: the fastest signal in either direction is the gravity
+    # wave sqrt(g h) of the deepest cell
+    sc = inputs.lake_at_rest(nx=32, ny=28, dx=1.0, dy=2.0, dtype=F64)
+    c = np.sqrt(9.81 * sc.h.max())
+    expect = sc.params.cfl / (c / 1.0 + c / 2.0)
+    assert abs(dt_of_first_step(sc.params, sc.fields()) - expect) <= 1e-14 * expect
+
+
+def test_time_step_of_uniform_flow_adds_the_flow_speed_along_x():
+    # uniform flow u along x on anisotropic cells: alpha_x = u + sqrt(g h),
+    # alpha_y = sqrt(g h)
+    sc = inputs.friction_channel(nx=64, dtype=F64)
+    p = dataclasses.replace(sc.params, cfl=0.4, dt_fixed=0.0, dx=10.0, dy=25.0)
+    u = sc.meta["q0"] / sc.meta["depth"]
+    c = np.sqrt(9.81 * sc.meta["depth"])
+    expect = 0.4 / ((u + c) / 10.0 + c / 25.0)
+    assert abs(dt_of_first_step(p, sc.fields()) - expect) <= 1e-14 * expect
+
+
+def test_runup_is_the_highest_wet_bed_reached():
+    # a lake against a planar beach with a wave offshore: the runup is the
+    # highest bed above the datum under water deeper than h_dry, over the
+    # starting state and the state after every step (brute force over that
+    # definition on a small grid)
+    nx, ny, dx = 60, 5, 1.0
+    X = (np.arange(nx) + 0.5) * dx
+    b = np.tile(0.05 * (X - 30.0), (ny, 1))
+    h = np.maximum(0.3 + 0.4 * np.exp(-((X - 12.0) / 4.0) ** 2) - b, 0.0)
+    z = np.zeros_like(b)
+    p = inputs.Params(nx, ny, dx, dx, cfl=0.4)
+    o = oracle.Oracle(p, b, z, h, z, z)
+
+    def highest_wet_bed(depth):
+        m = (b > 0) & (depth > p.h_dry)
+        return b[m].max() if m.any() else 0.0
+
+    best = highest_wet_bed(h)
+    assert o.scalars()["runup"] == best
+    for _ in range(120):
+        assert o.step(1) == 0
+        best = max(best, highest_wet_bed(o.state()[0]))
+        assert o.scalars()["runup"] == best
+    assert best > highest_wet_bed(h)  # the wave climbed the beach
