@@ -131,7 +131,8 @@ void swe_destroy(swe_ctx *ctx);
  * (1/3, 2/3).  Stable for any friction stiffness; first order in dt where the
  * friction dominates.  0 (default): the explicit term of the paper.  Can be
  * switched at any time (the captured graph is dropped); other values are
- * SWE_EINVAL.  Contexts only: batches and servers use the explicit term. */
+ * SWE_EINVAL.  Batches and servers take it through swe_batch_set_option and
+ * swe_server_set_option. */
 #define SWE_OPT_FRICTION_IMPLICIT 4
 int swe_set_option(swe_ctx *ctx, int32_t key, int64_t value);
 
@@ -230,6 +231,11 @@ int swe_batch_set_mode(swe_batch *bt, int32_t mode, int32_t use_graph);
 /* Tile variant used by the batch's launches (-1: automatic, from the
  * scenario with most cells).  All variants give bitwise identical states. */
 int swe_batch_set_tile(swe_batch *bt, int32_t tile);
+/* Batch option: only SWE_OPT_FRICTION_IMPLICIT (0 or 1; Methods, the
+ * friction variant described at that key), for every scenario of the batch
+ * from the next swe_batch_run on.  A scenario then advances bitwise as a
+ * context with the same option.  Other keys or values are SWE_EINVAL. */
+int swe_batch_set_option(swe_batch *bt, int32_t key, int64_t value);
 /* Maximum-depth map of scenario `index`, as swe_track_max_depth for a
  * single scenario: with enable != 0 keep per cell the maximum of h over its
  * state at the call and after every later step of this batch (the map is
@@ -309,6 +315,11 @@ int swe_poll_ex(swe_server *sv, uint64_t ticket, swe_result *r, float *h, float 
 /* Launch mode of the server's segments (SWE_BATCH_ROUNDS, the default, or
  * SWE_BATCH_PERSISTENT); takes effect at the next segment. */
 int swe_server_set_mode(swe_server *sv, int32_t mode);
+/* Server option: only SWE_OPT_FRICTION_IMPLICIT (0 or 1), for every request;
+ * settable before the first submit only (SWE_EBUSY after it), so that all
+ * requests share one friction treatment.  Other keys or values are
+ * SWE_EINVAL. */
+int swe_server_set_option(swe_server *sv, int32_t key, int64_t value);
 
 /* Cancel a queued or running request (it ends as SWE_CANCELLED). */
 int swe_cancel(swe_server *sv, uint64_t ticket);

@@ -31,112 +31,11 @@
 #include <numeric>
 #include <vector>
 
+#include "swe_batch_kernels.hpp"
 #include "swe_internal.hpp"
 #include "swe_schedule.hpp"
 
 namespace swe {
-
-__device__ __forceinline__ int xcd_remap_b(int b, int nb)
-{
-    const int q = nb >> 3, r = nb & 7;
-    const int x = b & 7, l = b >> 3;
-    return x * q + (x < r ? x : r) + l;
-}
-
-// Largest i in [0, n) with a[i] <= v (a ascending, a[0] <= v).
-template <class T>
-__device__ __forceinline__ int upper_index(const T *a, int n, T v)
-{
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (a[mid] <= v) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-struct BatchTables {
-    const Geo *geo;            // per scenario (batch order)
-    const int *order;          // sorted position -> scenario
-    const int *prefix;         // tile prefix over sorted positions (size nact + 1)
-    const int *ntx;            // tiles along x per sorted position
-    const long long *rstart;   // first ticket of each round (size nrounds + 1)
-    const int *ractive;        // active prefix length per round
-    unsigned int *done;        // completed tiles per sorted position (this run)
-    unsigned long long *ticket;
-    int nrounds, nact, group;
-};
-
-template <class C, int W>
-__global__ __launch_bounds__(C::NT, W) void k_persistent(BatchTables T)
-{
-    __shared__ float lds[C::LDS_FLOATS];
-    __shared__ long long s_ticket;
-    const long long total = T.rstart[T.nrounds];
-    for (;;) {
-        if (threadIdx.x == 0) s_ticket = (long long)atomicAdd(T.ticket, (unsigned long long)T.group);
-        __syncthreads();
-        const long long t0 = s_ticket;
-        __syncthreads();
-        if (t0 >= total) break;
-        const long long t1 = t0 + T.group < total ? t0 + T.group : total;
-        int r = upper_index(T.rstart, T.nrounds, t0);
-        long long t = t0;
-        // The grabbed tickets are handled in runs that stay inside one round.
-        // Tiles of one round never depend on each other, so a run waits once
-        // (one acquire) for the previous round of every scenario it touches,
-        // runs its tiles, and publishes them with one release.
-        while (t < t1) {
-            const long long te = t1 < T.rstart[r + 1] ? t1 : T.rstart[r + 1];
-            const int l0 = (int)(t - T.rstart[r]), l1 = (int)(te - T.rstart[r]);
-            const int s0 = upper_index(T.prefix, T.ractive[r], l0);
-            const int s1 = upper_index(T.prefix, T.ractive[r], l1 - 1);
-            if (threadIdx.x == 0) {
-                for (int sl = s0; sl <= s1; ++sl) {
-                    const unsigned int need = (unsigned int)(T.prefix[sl + 1] - T.prefix[sl]) * (unsigned int)r;
-                    while (__hip_atomic_load(&T.done[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need)
-                        __builtin_amdgcn_s_sleep(1);
-                }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
-            __syncthreads();
-            int slot = s0;
-            for (int l = l0; l < l1; ++l) {
-                while (l >= T.prefix[slot + 1]) ++slot;
-                const int tl = l - T.prefix[slot];
-                const int ntx = T.ntx[slot];
-                stage_tile<C, false>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, r % 3 + 1);
-                __syncthreads();
-            }
-            // every wave makes its own stores visible at agent scope before
-            // the barrier; then one thread publishes the run
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                for (int sl = s0; sl <= s1; ++sl) {
-                    const int a = l0 > T.prefix[sl] ? l0 : T.prefix[sl];
-                    const int b = l1 < T.prefix[sl + 1] ? l1 : T.prefix[sl + 1];
-                    __hip_atomic_fetch_add(&T.done[sl], (unsigned int)(b - a), __ATOMIC_RELEASE,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                }
-            }
-            t = te;
-            ++r;
-        }
-    }
-}
-
-template <class C, int S, int W>
-__global__ __launch_bounds__(C::NT, W) void k_round(BatchTables T, int nact_round, int nblocks)
-{
-    __shared__ float lds[C::LDS_FLOATS];
-    const int id = xcd_remap_b(blockIdx.x, nblocks);
-    const int slot = upper_index(T.prefix, nact_round, id);
-    const int tl = id - T.prefix[slot];
-    const int ntx = T.ntx[slot];
-    stage_tile<C, (W <= 2)>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, S);
-}
 
 // Clears the run's counters (a kernel, so graph replays need no memset node).
 __global__ void k_zero_counters(unsigned int *done, int n, unsigned long long *ticket)
@@ -145,20 +44,8 @@ __global__ void k_zero_counters(unsigned int *done, int n, unsigned long long *t
     if (threadIdx.x == 0) *ticket = 0ull;
 }
 
-struct BatchKernels {
-    void (*persistent)(BatchTables);
-    void (*round[3])(BatchTables, int, int);
-};
-
-#define SWE_BK(TX, TY, R, W)                                                                  \
-    {k_persistent<TileCfg<TX, TY, R>, W>,                                                     \
-     {k_round<TileCfg<TX, TY, R>, 1, W>, k_round<TileCfg<TX, TY, R>, 2, W>,                    \
-      k_round<TileCfg<TX, TY, R>, 3, W>}},
-
-// same order as the single-scenario variant table
-static const BatchKernels g_bk[] = {SWE_BK(64, 16, 8, 2) SWE_BK(64, 32, 8, 2) SWE_BK(32, 32, 8, 2)
-                                        SWE_BK(64, 16, 4, 2) SWE_BK(128, 16, 8, 2) SWE_BK(64, 16, 4, 3)
-                                            SWE_BK(32, 32, 4, 3) SWE_BK(32, 16, 2, 2) SWE_BK(16, 16, 2, 2) SWE_BK(16, 16, 1, 2)};
+#define SWE_BK_EXPLICIT(TX, TY, R, W) SWE_BK(TX, TY, R, W, false)
+const BatchKernels g_bk[] = {SWE_TILE_LIST(SWE_BK_EXPLICIT)};
 
 // ---------------------------------------------------------------------------
 // segment launcher (shared by swe_batch and the server)
@@ -172,10 +59,10 @@ SegmentLauncher::~SegmentLauncher()
 }
 
 int SegmentLauncher::run(const std::vector<Geo> &geos, const std::vector<int> &ksteps, int vi, int mode,
-                         bool use_graph, hipStream_t stream)
+                         bool use_graph, hipStream_t stream, bool implicit)
 {
     const Variant &v = variant(vi);
-    const BatchKernels &K = g_bk[vi];
+    const BatchKernels &K = implicit ? g_bk_imp[vi] : g_bk[vi];
     const int n = (int)geos.size();
     std::vector<int> nxs(n), nys(n);
     for (int i = 0; i < n; ++i) {
@@ -301,6 +188,7 @@ struct swe_batch {
     int mode = SWE_BATCH_ROUNDS;
     bool use_graph = true;
     int tile = -1;
+    bool implicit = false;  // point-implicit friction
     SegmentLauncher seg;
 };
 
@@ -373,6 +261,13 @@ int swe_batch_set_tile(swe_batch *bt, int32_t tile)
     return SWE_OK;
 }
 
+int swe_batch_set_option(swe_batch *bt, int32_t key, int64_t value)
+{
+    if (!bt || key != SWE_OPT_FRICTION_IMPLICIT || (value != 0 && value != 1)) return SWE_EINVAL;
+    bt->implicit = value != 0;
+    return SWE_OK;
+}
+
 int swe_batch_run(swe_batch *bt, int32_t max_steps)
 {
     if (!bt) return SWE_EINVAL;
@@ -384,7 +279,7 @@ int swe_batch_run(swe_batch *bt, int32_t max_steps)
         geos.push_back(s.d.geo);
         ks.push_back(k);
     }
-    const int rc = bt->seg.run(geos, ks, batch_variant(bt), bt->mode, bt->use_graph, bt->stream);
+    const int rc = bt->seg.run(geos, ks, batch_variant(bt), bt->mode, bt->use_graph, bt->stream, bt->implicit);
     if (rc) return rc;
     for (size_t i = 0; i < bt->sc.size(); ++i) bt->sc[i].done += ks[i];
     return SWE_OK;

@@ -1,0 +1,128 @@
+// swe_batch_kernels.hpp - the batched stage kernels (persistent and per-round
+// launches) and their tables; the schedule is described in swe_batch.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "swe_internal.hpp"
+
+namespace swe {
+
+__device__ __forceinline__ int xcd_remap_b(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, l = b >> 3;
+    return x * q + (x < r ? x : r) + l;
+}
+
+// Largest i in [0, n) with a[i] <= v (a ascending, a[0] <= v).
+template <class T>
+__device__ __forceinline__ int upper_index(const T *a, int n, T v)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+struct BatchTables {
+    const Geo *geo;            // per scenario (batch order)
+    const int *order;          // sorted position -> scenario
+    const int *prefix;         // tile prefix over sorted positions (size nact + 1)
+    const int *ntx;            // tiles along x per sorted position
+    const long long *rstart;   // first ticket of each round (size nrounds + 1)
+    const int *ractive;        // active prefix length per round
+    unsigned int *done;        // completed tiles per sorted position (this run)
+    unsigned long long *ticket;
+    int nrounds, nact, group;
+};
+
+template <class C, int W, bool IMP>
+__global__ __launch_bounds__(C::NT, W) void k_persistent(BatchTables T)
+{
+    __shared__ float lds[C::LDS_FLOATS];
+    __shared__ long long s_ticket;
+    const long long total = T.rstart[T.nrounds];
+    for (;;) {
+        if (threadIdx.x == 0) s_ticket = (long long)atomicAdd(T.ticket, (unsigned long long)T.group);
+        __syncthreads();
+        const long long t0 = s_ticket;
+        __syncthreads();
+        if (t0 >= total) break;
+        const long long t1 = t0 + T.group < total ? t0 + T.group : total;
+        int r = upper_index(T.rstart, T.nrounds, t0);
+        long long t = t0;
+        // The grabbed tickets are handled in runs that stay inside one round.
+        // Tiles of one round never depend on each other, so a run waits once
+        // (one acquire) for the previous round of every scenario it touches,
+        // runs its tiles, and publishes them with one release.
+        while (t < t1) {
+            const long long te = t1 < T.rstart[r + 1] ? t1 : T.rstart[r + 1];
+            const int l0 = (int)(t - T.rstart[r]), l1 = (int)(te - T.rstart[r]);
+            const int s0 = upper_index(T.prefix, T.ractive[r], l0);
+            const int s1 = upper_index(T.prefix, T.ractive[r], l1 - 1);
+            if (threadIdx.x == 0) {
+                for (int sl = s0; sl <= s1; ++sl) {
+                    const unsigned int need = (unsigned int)(T.prefix[sl + 1] - T.prefix[sl]) * (unsigned int)r;
+                    while (__hip_atomic_load(&T.done[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need)
+                        __builtin_amdgcn_s_sleep(1);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            __syncthreads();
+            int slot = s0;
+            for (int l = l0; l < l1; ++l) {
+                while (l >= T.prefix[slot + 1]) ++slot;
+                const int tl = l - T.prefix[slot];
+                const int ntx = T.ntx[slot];
+                stage_tile<C, false, false, IMP>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, r % 3 + 1);
+                __syncthreads();
+            }
+            // every wave makes its own stores visible at agent scope before
+            // the barrier; then one thread publishes the run
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                for (int sl = s0; sl <= s1; ++sl) {
+                    const int a = l0 > T.prefix[sl] ? l0 : T.prefix[sl];
+                    const int b = l1 < T.prefix[sl + 1] ? l1 : T.prefix[sl + 1];
+                    __hip_atomic_fetch_add(&T.done[sl], (unsigned int)(b - a), __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            t = te;
+            ++r;
+        }
+    }
+}
+
+template <class C, int S, int W, bool IMP>
+__global__ __launch_bounds__(C::NT, W) void k_round(BatchTables T, int nact_round, int nblocks)
+{
+    __shared__ float lds[C::LDS_FLOATS];
+    const int id = xcd_remap_b(blockIdx.x, nblocks);
+    const int slot = upper_index(T.prefix, nact_round, id);
+    const int tl = id - T.prefix[slot];
+    const int ntx = T.ntx[slot];
+    stage_tile<C, (W <= 2), false, IMP>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, S);
+}
+
+struct BatchKernels {
+    void (*persistent)(BatchTables);
+    void (*round[3])(BatchTables, int, int);
+};
+
+// Kernels of one tile variant; IMP: point-implicit friction.
+#define SWE_BK(TX, TY, R, W, IMP)                                                             \
+    {k_persistent<TileCfg<TX, TY, R>, W, IMP>,                                                \
+     {k_round<TileCfg<TX, TY, R>, 1, W, IMP>, k_round<TileCfg<TX, TY, R>, 2, W, IMP>,          \
+      k_round<TileCfg<TX, TY, R>, 3, W, IMP>}},
+// In SWE_TILE_LIST order, the same as the single-scenario variant table;
+// the explicit-friction set lives in swe_batch.hip, the implicit one in
+// swe_batch_imp.hip (compiled in parallel).
+extern const BatchKernels g_bk[], g_bk_imp[];
+
+}  // namespace swe

@@ -124,8 +124,9 @@ struct SegmentLauncher {
     int cus = 0;
     int group = 0;  // tickets taken per atomic in persistent mode (0: automatic)
     ~SegmentLauncher();
+    // implicit: the point-implicit friction kernels
     int run(const std::vector<Geo> &geos, const std::vector<int> &ksteps, int vi, int mode, bool use_graph,
-            hipStream_t stream);
+            hipStream_t stream, bool implicit = false);
 };
 
 }  // namespace swe

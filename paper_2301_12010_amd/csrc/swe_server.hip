@@ -127,6 +127,7 @@ struct swe_server {
     int max_slots = 64;
     int segment_steps = 100;
     int mode = SWE_BATCH_ROUNDS;
+    bool implicit = false;  // point-implicit friction (set before the first submit)
     size_t max_queue = 1 << 16;
     Arena arena;
     hipStream_t compute = nullptr, copy = nullptr;
@@ -212,11 +213,14 @@ void swe_server::loop()
             for (size_t i = 1; i < geos.size(); ++i)
                 if ((size_t)geos[i].nx * geos[i].ny > (size_t)geos[big].nx * geos[big].ny) big = (int)i;
             int launch_mode;
+            bool launch_implicit;
             {
                 std::lock_guard<std::mutex> lk(mu);
                 launch_mode = mode;
+                launch_implicit = implicit;
             }
-            rc = seg.run(geos, ks, default_variant(geos[big].nx, geos[big].ny), launch_mode, false, compute);
+            rc = seg.run(geos, ks, default_variant(geos[big].nx, geos[big].ny), launch_mode, false, compute,
+                         launch_implicit);
             std::lock_guard<std::mutex> lk(mu);
             ++segments;
             if (rc) fatal = rc;
@@ -414,6 +418,15 @@ int swe_server_set_mode(swe_server *sv, int32_t mode)
     if (!sv || (mode != SWE_BATCH_PERSISTENT && mode != SWE_BATCH_ROUNDS)) return SWE_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
     sv->mode = mode;
+    return SWE_OK;
+}
+
+int swe_server_set_option(swe_server *sv, int32_t key, int64_t value)
+{
+    if (!sv || key != SWE_OPT_FRICTION_IMPLICIT || (value != 0 && value != 1)) return SWE_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->submitted > 0) return SWE_EBUSY;  // one treatment for every request
+    sv->implicit = value != 0;
     return SWE_OK;
 }
 

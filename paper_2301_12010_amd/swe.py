@@ -103,6 +103,7 @@ _SIGS = {
     "swe_batch_read": (ctypes.c_int, [_VP, ctypes.c_int32, _FP, _FP, _FP, ctypes.POINTER(Stats)]),
     "swe_batch_set_mode": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "swe_batch_set_tile": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "swe_batch_set_option": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int64]),
     "swe_batch_track_max_depth": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "swe_batch_read_max_depth": (ctypes.c_int, [_VP, ctypes.c_int32, _FP]),
     "swe_batch_destroy": (None, [_VP]),
@@ -116,6 +117,7 @@ _SIGS = {
     "swe_poll_ex": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(Result), _FP, _FP, _FP, _FP]),
     "swe_cancel": (ctypes.c_int, [_VP, ctypes.c_uint64]),
     "swe_server_set_mode": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "swe_server_set_option": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int64]),
     "swe_server_get_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ServerStats)]),
     "swe_server_destroy": (None, [_VP]),
     "swe_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -393,6 +395,9 @@ class Batch:
     def set_tile(self, tile: int):
         _check(_lib().swe_batch_set_tile(self._bt, int(tile)), "swe_batch_set_tile")
 
+    def set_option(self, key: int, value: int):
+        _check(_lib().swe_batch_set_option(self._bt, int(key), int(value)), "swe_batch_set_option")
+
     def run(self, max_steps: int = -1):
         _check(_lib().swe_batch_run(self._bt, int(max_steps)), "swe_batch_run")
 
@@ -483,6 +488,9 @@ class Server:
 
     def set_mode(self, mode: int):
         _check(_lib().swe_server_set_mode(self._sv, int(mode)), "swe_server_set_mode")
+
+    def set_option(self, key: int, value: int):
+        _check(_lib().swe_server_set_option(self._sv, int(key), int(value)), "swe_server_set_option")
 
     def cancel(self, ticket: int):
         _check(_lib().swe_cancel(self._sv, int(ticket)), "swe_cancel")

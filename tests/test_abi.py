@@ -64,6 +64,8 @@ def test_host_only_calls():
     assert L.swe_read_max_depth(None, None) == swe.EINVAL
     assert L.swe_batch_track_max_depth(None, 0, 1) == swe.EINVAL
     assert L.swe_batch_read_max_depth(None, 0, None) == swe.EINVAL
+    assert L.swe_batch_set_option(None, swe.OPT_FRICTION_IMPLICIT, 1) == swe.EINVAL
+    assert L.swe_server_set_option(None, swe.OPT_FRICTION_IMPLICIT, 1) == swe.EINVAL
     # allocator hook: both callbacks or neither
     assert L.swe_set_allocator(swe.ALLOC_FN(lambda n, d, u: None), swe.RELEASE_FN(), None) == swe.EINVAL
     assert L.swe_set_allocator(swe.ALLOC_FN(), swe.RELEASE_FN(lambda p, d, u: None), None) == swe.EINVAL

@@ -147,3 +147,60 @@ def test_option_values():
     s.step(3)
     assert s.read()[3]["step"] == 6
     s.close()
+
+
+def alone_implicit(sc, n):
+    s = swe.Solver.from_scenario(sc)
+    s.set_option(swe.OPT_FRICTION_IMPLICIT, 1)
+    s.step(n)
+    out = s.read()
+    s.close()
+    return out
+
+
+MIX = [(inputs.random_wet(64, 48, seed=51, dry_fraction=0.1, manning=0.05), 13),
+       (inputs.random_wet(130, 70, seed=52, manning=0.08), 7),
+       (inputs.friction_channel(nx=150, dt_fixed=0.25), 10)]
+
+
+@pytest.mark.parametrize("mode,graph", [(swe.BATCH_ROUNDS, True), (swe.BATCH_PERSISTENT, False)])
+def test_batch_with_implicit_friction_equals_alone(mode, graph):
+    say(f"batch mode={mode} graph={graph}")
+    bt = swe.Batch()
+    bt.set_option(swe.OPT_FRICTION_IMPLICIT, 1)
+    bt.set_mode(mode, graph)
+    idx = [bt.add_scenario(sc, n) for sc, n in MIX]
+    bt.run()
+    for i, (sc, n) in zip(idx, MIX):
+        got = bt.read(i)
+        ref = alone_implicit(sc, n)
+        for a, b in zip(got[:3], ref[:3]):
+            assert np.array_equal(a, b), sc.name
+        assert got[3]["t"] == ref[3]["t"]
+    with pytest.raises(swe.SweError):
+        bt.set_option(swe.OPT_FRICTION_IMPLICIT, 2)
+    with pytest.raises(swe.SweError):
+        bt.set_option(swe.OPT_TILE, 1)
+    bt.close()
+
+
+def test_server_with_implicit_friction_equals_alone():
+    import time
+    sv = swe.Server(mem_budget=256 << 20, max_slots=8, segment_steps=4)
+    sv.set_option(swe.OPT_FRICTION_IMPLICIT, 1)
+    tickets = [sv.submit_scenario(sc, n) for sc, n in MIX]
+    with pytest.raises(swe.SweError) as e:
+        sv.set_option(swe.OPT_FRICTION_IMPLICIT, 0)  # requests already submitted
+    assert e.value.code == swe.EBUSY
+    t0 = time.time()
+    for t, (sc, n) in zip(tickets, MIX):
+        r, state = sv.poll(t)
+        while r["status"] == swe.PENDING:
+            assert time.time() - t0 < 60, "server did not finish in time"
+            time.sleep(0.002)
+            r, state = sv.poll(t)
+        assert r["status"] == swe.DONE
+        ref = alone_implicit(sc, n)
+        for a, b in zip(state, ref[:3]):
+            assert np.array_equal(a, b), sc.name
+    sv.close()
