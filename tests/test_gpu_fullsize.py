@@ -60,21 +60,24 @@ def test_large_coast_first_steps_against_checker(coast):
     assert abs(g[3]["t"] - rs["t"]) <= 1e-6 * rs["t"]
 
 
-def test_large_coast_first_steps_with_implicit_friction(coast):
-    # the same at full size with point-implicit friction, in the launch
-    # configuration the bench times for it (autotuned tile, graph replays)
+@pytest.mark.parametrize("implicit,compensated", [(1, 0), (0, 1)])
+def test_large_coast_first_steps_with_options(coast, implicit, compensated):
+    # the same at full size with point-implicit friction or the compensated
+    # level, in the launch configuration the bench times for them
+    # (autotuned tile, graph replays)
     n = 10
     tile, _ = swe.autotune(coast.params.nx, coast.params.ny)
     s = swe.Solver.from_scenario(coast)
     s.set_option(swe.OPT_TILE, tile)
     s.set_option(swe.OPT_GRAPH_STEPS, 5)
-    s.set_option(swe.OPT_FRICTION_IMPLICIT, 1)
+    s.set_option(swe.OPT_FRICTION_IMPLICIT, implicit)
+    s.set_option(swe.OPT_COMPENSATED, compensated)
     s.step(n)
     g = s.read()
     s.close()
-    say(f"gpu done; checker {n} steps on the host (implicit friction)", g[3])
+    say(f"gpu done; checker {n} steps on the host (implicit {implicit}, compensated {compensated})", g[3])
     o = oracle.Oracle.from_scenario(coast)
-    o.set_friction(True)
+    o.set_friction(bool(implicit))
     assert o.step(n) == 0
     e_h, e_hu, e_hv, dm, frac = front_split_errors(g, o.state())
     say("full-size errors", e_h, e_hu, e_hv, "front band", dm, frac)
