@@ -12,8 +12,13 @@
  *     of b reconstructed with the normal-momentum flux's WENO weights, and the
  *     explicit Manning friction -g n^2 |q| q / h^(7/3) (Eqs. (2)-(3), (7));
  *   - the three-stage TVD Runge-Kutta update of Eq. (8).
+ * Options (off by default): point-implicit friction in place of the explicit
+ * term (SWE_OPT_FRICTION_IMPLICIT) and a compensated FP32 level
+ * (SWE_OPT_COMPENSATED).
  * All arithmetic of the state is FP32 on the GPU; FP64 is kept for time and
- * the mass diagnostics.  No call takes or returns a torch type.
+ * the mass diagnostics.  No call takes or returns a torch type.  Device
+ * memory comes from hipMalloc or from a caller allocator
+ * (swe_set_allocator).
  *
  * Arrays are row-major [ny][nx] float32 with x fastest (element (i, j) at
  * j * nx + i).  Input and output pointers may be host or device memory; the
