@@ -124,3 +124,28 @@ def test_failing_allocator_reads_as_out_of_memory():
     s.step(5)
     assert s.read()[3]["step"] == 5
     s.close()
+
+
+def test_misaligned_memory_is_handed_back():
+    # memory not aligned to 256 bytes is released at once and the call fails
+    # with SWE_EINVAL; no kernel ever sees it
+    torch.cuda.synchronize()
+    m0 = torch.cuda.memory_allocated()
+    released = []
+
+    def alloc(nbytes, dev):
+        return torch.cuda.caching_allocator_alloc(nbytes + 256, dev) + 4
+
+    def release(ptr, dev):
+        released.append(ptr)
+        torch.cuda.caching_allocator_delete(ptr - 4)
+
+    swe.set_allocator(alloc, release)
+    try:
+        with pytest.raises(swe.SweError) as e:
+            swe.Solver.from_scenario(inputs.dam_break())
+        assert e.value.code == swe.EINVAL
+    finally:
+        swe.set_allocator(None, None)
+    assert len(released) == 1 and released[0] % 256 == 4
+    assert torch.cuda.memory_allocated() == m0
