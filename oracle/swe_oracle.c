@@ -10,8 +10,9 @@
  * "Leveraging Google's Tensor Processing Units for tsunami-risk mitigation
  * planning in the Pacific Northwest and beyond"):
  *   - Methods, Eqs. (1)-(3): the nonlinear shallow-water system with the
- *     1/2 g (h^2 - b^2) pressure flux, bed source -g (h+b) grad b and the
- *     explicit Manning friction -g n^2 |q| q / h^(7/3);
+ *     1/2 g (h^2 - b^2) pressure flux, bed source -g (h+b) grad b (taken
+ *     relative to the datum, R2) and the explicit Manning friction
+ *     -g n^2 |q| q / h^(7/3);
  *   - Methods, Eq. (4): the vector form u_t + F_x + G_y = S, u = (h, hu, hv);
  *   - Methods, WENO paragraph and Eq. (5): fifth-order WENO reconstruction,
  *     one value for each characteristic direction at every half-step face;
@@ -25,12 +26,22 @@
  *   R1  WENO acts on the split fluxes F+- = (F +- alpha u~)/2 at the faces
  *       (finite-difference flux splitting); the printed LF formula, which
  *       multiplies alpha by a flux difference, is read as this split form.
- *   R2  u~ = (h + b, hu, hv): the mass component of the LF viscosity acts on
- *       the surface h + b, and the face value of b used by the bed source is
- *       reconstructed with the nonlinear weights of the hu (x) or hv (y)
- *       split flux.  Together these make still water over any smooth bed an
- *       exact discrete steady state (the bed treatment the paper takes from
- *       Xing & Shu).
+ *   R2  The bed enters relative to the datum (the still-water level, 0):
+ *       with m = min(b, 0) the pressure flux is 1/2 g (h^2 - m^2), the bed
+ *       source -g (h + m) db/dx, and u~ = (h + m, hu, hv), so the mass
+ *       component of the LF viscosity acts on h + m.  Below the datum m = b
+ *       and this is the printed form (Eqs. (1)-(3)): 1/2 g (h^2 - b^2),
+ *       -g (h + b) grad b, viscosity on the surface h + b.  On land m = 0 and
+ *       it is 1/2 g h^2, -g h grad b, viscosity on the depth.  Both forms
+ *       are the same differential system (d(m^2)/dx = 2 m db/dx wherever m
+ *       is not constant), but the printed one, read literally on dry land
+ *       (h = 0), has the flux -1/2 g b^2 and a viscosity on b between dry
+ *       cells, which the clamp of R7 turns into water appearing on land.
+ *       The face value of b used by the bed source is reconstructed with the
+ *       nonlinear weights of the hu (x) or hv (y) split flux.  Together these
+ *       make still water at any level over a bed below the datum, and still
+ *       water at the datum next to any dry land, exact discrete steady
+ *       states (the bed treatment the paper takes from Xing & Shu).
  *   R3  alpha_x = max(|u| + sqrt(g h+)), alpha_y = max(|v| + sqrt(g h+)) over
  *       the interior cells of each stage's input, one per scenario.
  *   R4  dt = cfl / (alpha_x/dx + alpha_y/dy) from u^n, held over the three
@@ -280,6 +291,12 @@ static double time_step(const oracle_ctx *c, double ax, double ay)
 /* w is extended with ghosts filled.                                          */
 /* ------------------------------------------------------------------------ */
 
+/* The bed relative to the datum (R2): b below it, 0 on land. */
+static inline double datum_bed(double b)
+{
+    return b < 0.0 ? b : 0.0;
+}
+
 /* Cell flux F (x) or G (y) and the LF-split vector u~ of one cell.  dir 0 = x. */
 static void cell_flux(const oracle_ctx *c, int dir, double h, double hu, double hv, double b,
                       double F[3], double U[3])
@@ -289,7 +306,8 @@ static void cell_flux(const oracle_ctx *c, int dir, double h, double hu, double 
         u = hu / h;
         v = hv / h;
     }
-    const double pres = 0.5 * c->p.g * (h * h - b * b);
+    const double m = datum_bed(b);
+    const double pres = 0.5 * c->p.g * (h * h - m * m);
     if (dir == 0) {
         F[0] = hu;
         F[1] = hu * u + pres;
@@ -299,7 +317,7 @@ static void cell_flux(const oracle_ctx *c, int dir, double h, double hu, double 
         F[1] = hv * u;
         F[2] = hv * v + pres;
     }
-    U[0] = h + b;
+    U[0] = h + m;
     U[1] = hu;
     U[2] = hv;
 }
@@ -386,7 +404,7 @@ static void rhs(oracle_ctx *c, const double *h, const double *hu, const double *
                        d0, d1, d2, db, Fp, Fm, Fhat, bhat);
             for (int i = 0; i < nx; i++) {
                 const size_t o = II(c, i, j);
-                const double eta = h[IX(c, i, j)] + c->b[IX(c, i, j)];
+                const double eta = h[IX(c, i, j)] + datum_bed(c->b[IX(c, i, j)]);
                 c->fx[0][o] = d0[i];
                 c->fx[1][o] = d1[i];
                 c->fx[2][o] = d2[i];
@@ -405,7 +423,7 @@ static void rhs(oracle_ctx *c, const double *h, const double *hu, const double *
                        d0, d1, d2, db, Fp, Fm, Fhat, bhat);
             for (int j = 0; j < ny; j++) {
                 const size_t o = II(c, i, j);
-                const double eta = h[IX(c, i, j)] + c->b[IX(c, i, j)];
+                const double eta = h[IX(c, i, j)] + datum_bed(c->b[IX(c, i, j)]);
                 c->gy[0][o] = d0[j];
                 c->gy[1][o] = d1[j];
                 c->gy[2][o] = d2[j];

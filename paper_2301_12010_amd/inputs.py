@@ -145,18 +145,24 @@ def parabolic_bowl(nx: int = 600, ny: int = 8, dx: float = 1.0, h0: float = 1.0,
 
 def steady_slope(nx: int = 64, ny: int = 4, dx: float = 1.0, depth: float = 0.5,
                  slope: float = 1.0 / 20.0, manning: float = 0.033,
-                 perturb: float = 0.0, cfl: float = 0.4, dtype=np.float32) -> Scenario:
+                 perturb: float = 0.0, cfl: float = 0.4, b0: float = -1.0,
+                 dtype=np.float32) -> Scenario:
     """Uniform friction-limited flow down a constant slope (Section 2.3).
 
-    The bed falls along +x with gradient ``slope``; the uniform unit discharge
-    of Manning's law is ``q = sqrt(slope)/n * depth^(5/3)``.  West and east
-    sides use frozen (FIXED) ghosts, north and south mirror ghosts.  A
-    non-zero ``perturb`` adds a Gaussian depth bump of relative height
-    ``perturb`` and radius L/10 at mid-channel (it is below 1e-10 at the ends,
-    so the frozen inflow ghosts keep the uniform state).
+    The bed falls along +x with gradient ``slope`` from ``b0`` at the west
+    face.  The default puts the bed and its linearly extended ghosts below
+    the datum (where the pressure flux is the paper's 1/2 g (h^2 - b^2)); a
+    ``b0`` high enough puts the whole channel on land above it (flux
+    1/2 g h^2, bed source -g h db/dx).  The uniform unit discharge of
+    Manning's law is
+    ``q = sqrt(slope)/n * depth^(5/3)``.  West and east sides use frozen
+    (FIXED) ghosts, north and south mirror ghosts.  A non-zero ``perturb``
+    adds a Gaussian depth bump of relative height ``perturb`` and radius L/10
+    at mid-channel (it is below 1e-10 at the ends, so the frozen inflow
+    ghosts keep the uniform state).
     """
     X, Y = _centres(nx, ny, dx, dx)
-    b = -slope * X
+    b = b0 - slope * X
     q = np.sqrt(slope) / manning * depth ** (5.0 / 3.0)
     h = np.full((ny, nx), depth)
     if perturb:
@@ -170,6 +176,32 @@ def steady_slope(nx: int = 64, ny: int = 4, dx: float = 1.0, depth: float = 0.5,
     return Scenario("steady_slope", p, f(b), f(np.full((ny, nx), manning)),
                     f(h), f(hu), f(z), 0, dict(q=q, depth=depth, slope=slope,
                                                manning=manning))
+
+
+def still_coast(nx: int = 64, ny: int = 48, dx: float = 2.0, seed: int = 11,
+                manning: float = 0.025, kappa_cap: float = 1.0, dtype=np.float32) -> Scenario:
+    """Sea at rest at the datum against a beach with hills and a dry island.
+
+    The beach rises along +x (1/20) through the datum at 0.6 Lx; a Gaussian
+    island (4 m high, radius 10 m) stands in the sea at 0.3 Lx with its top
+    above the datum, and 2-4 seeded Gaussian hills (3-6 m, radius 6-14 m)
+    stand on the land.  Every cell below the datum holds water up to it and
+    every cell above it is dry: the exact solution is the initial state.
+    Reflective walls.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X, Y = _centres(nx, ny, dx, dx)
+    Lx, Ly = nx * dx, ny * dx
+    b = 0.05 * (X - 0.6 * Lx) + _gauss(X, Y, 4.0, 10.0, 0.3 * Lx, 0.5 * Ly)
+    for _ in range(int(rng.integers(2, 5))):
+        b = b + _gauss(X, Y, rng.uniform(3.0, 6.0), rng.uniform(6.0, 14.0),
+                       rng.uniform(0.7 * Lx, 0.95 * Lx), rng.uniform(0.0, Ly))
+    b = _f32(b, dtype)
+    h = _f32(np.maximum(-b.astype(np.float64), 0.0), dtype)
+    z = np.zeros((ny, nx))
+    p = Params(nx, ny, dx, dx, cfl=0.4, kappa_cap=kappa_cap)
+    return Scenario("still_coast", p, b, _f32(np.full((ny, nx), manning), dtype), h,
+                    _f32(z, dtype), _f32(z, dtype), 0, dict(seed=seed))
 
 
 def friction_channel(nx: int = 801, ny: int = 3, dx: float = 10.0, depth: float = 0.05,
@@ -192,12 +224,15 @@ def friction_channel(nx: int = 801, ny: int = 3, dx: float = 10.0, depth: float 
 
 def lake_at_rest(nx: int = 48, ny: int = 40, dx: float = 1.0, dy: float | None = None,
                  eta0: float = 1.7, seed: int = 7, nbumps: int = 6,
-                 depth: float = 1.0, manning: float = 0.0, cfl: float = 0.4,
+                 depth: float = 3.0, manning: float = 0.0, cfl: float = 0.4,
                  dtype=np.float32) -> Scenario:
     """Still water with a flat surface ``eta0`` over a smooth random bed.
 
-    The bed is ``eta0 - depth`` plus ``nbumps`` Gaussian bumps whose heights
-    keep every cell submerged, so the exact solution is the initial state.
+    The bed is ``eta0 - depth`` plus ``nbumps`` Gaussian bumps, capped a tenth
+    of ``depth`` below both the surface and the datum: every cell is
+    submerged and the bed lies below the datum, so the exact solution is the
+    initial state and the scheme keeps it exactly (``eta0`` is away from the
+    datum, so the pressure flux and the bed source do not vanish separately).
     """
     dy = dx if dy is None else dy
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -209,7 +244,7 @@ def lake_at_rest(nx: int = 48, ny: int = 40, dx: float = 1.0, dy: float | None =
         R = rng.uniform(0.08, 0.25) * min(Lx, Ly)
         cx, cy = rng.uniform(0, Lx), rng.uniform(0, Ly)
         b += A * np.exp(-(((X - cx) ** 2 + (Y - cy) ** 2) / R ** 2))
-    b = np.minimum(b, eta0 - 0.1 * depth)
+    b = np.minimum(b, min(eta0, 0.0) - 0.1 * depth)
     b = _f32(b, dtype)
     h = _f32(eta0 - b.astype(np.float64), dtype)
     z = np.zeros((ny, nx))

@@ -23,6 +23,7 @@ CASES = {
     "mitigation_1024_s1003": lambda: inputs.mitigation_coast(1024, 1024, 2.0, seed=1003),
     "uneven_s7": lambda: inputs.uneven_scenario(7),
     "deep_ocean_s5": lambda: inputs.deep_ocean(),
+    "still_coast_s11": lambda: inputs.still_coast(),
 }
 
 

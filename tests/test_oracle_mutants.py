@@ -174,13 +174,54 @@ def runup_flags(L):
     return o.scalars()["runup"] != b[m].max()
 
 
+def island_flags(L):
+    # sea at rest at the datum next to dry land with hills and an island
+    sc = inputs.still_coast(dtype=F64)
+    o = oracle.Oracle.from_scenario(sc, L=L)
+    if o.step(50) != 0:
+        return True
+    h, hu, hv = o.state()
+    ok = (np.abs(h - sc.h).max() <= 1e-13 and h[sc.b > 0].max() <= 1e-13
+          and max(np.abs(hu).max(), np.abs(hv).max()) <= 1e-12 and o.scalars()["runup"] == 0.0)
+    return not ok
+
+
+def land_slope_flags(L):
+    # uniform Manning flow down a slope that lies wholly above the datum
+    o = oracle.Oracle.from_scenario(inputs.steady_slope(b0=5.0, dtype=F64), L=L)
+    return not max(np.abs(a).max() for a in o.rhs()) < 2e-14
+
+
+def cap_flags(L):
+    # a stiff film with kappa_cap = 1: the discharge falls by exactly 3 per step
+    sc = inputs.friction_channel(manning=10.0, dt_fixed=0.5, kappa_cap=1.0, dtype=F64)
+    mid = sc.params.nx // 2
+    o = oracle.Oracle.from_scenario(sc, L=L)
+    q = sc.meta["q0"]
+    for _ in range(3):
+        if o.step(1) != 0:
+            return True
+        q /= 3.0
+        if not abs(o.state()[1][1, mid] - q) <= 1e-14 * q:
+            return True
+    return False
+
+
 MUTANTS = [
     # (id, anchor, replacement, detector)
-    ("surface_viscosity_on_h", "U[0] = h + b;", "U[0] = h;", lake_flags),
+    ("surface_viscosity_on_h", "U[0] = h + m;", "U[0] = h;", lake_flags),
+    ("printed_viscosity_on_dry_land", "U[0] = h + m;", "U[0] = h + b;", island_flags),
+    ("printed_pressure_on_dry_land", "(h * h - m * m)", "(h * h - b * b)", island_flags),
+    ("printed_form_everywhere", "return b < 0.0 ? b : 0.0;", "return b;", island_flags),
+    ("bed_coefficient_printed_on_land",
+     "const double eta = h[IX(c, i, j)] + datum_bed(c->b[IX(c, i, j)]);\n                c->fx[0][o]",
+     "const double eta = h[IX(c, i, j)] + c->b[IX(c, i, j)];\n                c->fx[0][o]", land_slope_flags),
+    ("friction_cap_removed", "if (kappa > cap)\n                    kappa = cap;", "", cap_flags),
+    ("friction_cap_times_dt", "c->p.kappa_cap / dt : INFINITY", "c->p.kappa_cap * dt : INFINITY", cap_flags),
     ("bed_weights_from_mass", "const int mb = dir == 0 ? 1 : 2;", "const int mb = 0;", lake_flags),
     ("bed_y_sign", "c->bedy[o] = -g * eta * db[j] / c->p.dy;",
      "c->bedy[o] = g * eta * db[j] / c->p.dy;", lake_flags),
-    ("pressure_drops_bed", "const double pres = 0.5 * c->p.g * (h * h - b * b);",
+    ("pressure_drops_bed", "const double pres = 0.5 * c->p.g * (h * h - m * m);",
      "const double pres = 0.5 * c->p.g * h * h;", lake_flags),
     ("minus_stencil_not_mirrored", "vm[s] = Fm[(k + 3 - s + HALO) * 3 + m];",
      "vm[s] = Fm[(k - 2 + s + HALO) * 3 + m];", dam_flags),

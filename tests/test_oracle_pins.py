@@ -151,7 +151,7 @@ def test_parabolic_bowl_converges():
     h0, a, L, amp = 1.0, 200.0, 600.0, 20.0
     T = 2 * np.pi / A.bowl_omega(h0, a)
     errs = []
-    for nx, dx in [(300, 2.0), (600, 1.0)]:
+    for nx, dx in [(300, 2.0), (600, 1.0), (1200, 0.5)]:
         sc = inputs.parabolic_bowl(nx=nx, ny=3, dx=dx, dtype=F64)
         o = oracle.Oracle.from_scenario(sc)
         s = run_to(o, 0.3 * T)
@@ -162,8 +162,10 @@ def test_parabolic_bowl_converges():
         core = A.bowl_h(x, s["t"], h0, a, L, amp) > 0.3
         u = hu[1][core] / h[1][core]
         assert abs(np.median(u) - A.bowl_u(s["t"], h0, a, amp)) < 0.05 * amp * A.bowl_omega(h0, a)
-    assert errs[0] < 0.05 and errs[1] < 0.02
-    assert errs[0] / errs[1] > 2.0
+    # the fronts are kinks of h moving over dry land: the error falls with
+    # dx, at less than second order (3.2e-3, 2.0e-3, 7.9e-4)
+    assert errs[0] < 5e-3
+    assert errs[0] / errs[1] > 1.4 and errs[1] / errs[2] > 1.4 and errs[0] / errs[2] > 3.0
 
 
 def test_mass_balance_with_clamping():
@@ -173,7 +175,7 @@ def test_mass_balance_with_clamping():
     m0 = o.scalars()["mass"]
     o.step(300)
     s = o.scalars()
-    assert s["clamp_mass"] > 1e-3 * m0
+    assert s["clamp_mass"] > 1e-4 * m0  # clamping is active (7.7e-4 of the mass)
     assert abs(s["mass"] - m0 - s["clamp_mass"]) <= 1e-12 * m0
 
 
@@ -221,6 +223,16 @@ def test_lake_at_rest_preserved_to_roundoff():
     assert np.abs(h + sc.b - 1.7).max() <= 1e-11
 
 
+def test_steady_slope_on_land_is_an_exact_discrete_steady_state():
+    # the same uniform flow with the whole channel above the datum, where the
+    # pressure flux is 1/2 g h^2 and the bed source -g h db/dx (reading R2):
+    # uniform h and linear b again make L(u) vanish to roundoff
+    sc = inputs.steady_slope(b0=5.0, dtype=F64)
+    assert sc.b.min() > 1.0
+    o = oracle.Oracle.from_scenario(sc)
+    assert max(np.abs(a).max() for a in o.rhs()) < 2e-14
+
+
 def test_lake_at_rest_with_friction_and_anisotropic_cells():
     sc = inputs.lake_at_rest(nx=40, ny=24, dx=1.0, dy=2.5, manning=0.05, dtype=F64)
     o = oracle.Oracle.from_scenario(sc)
@@ -228,6 +240,45 @@ def test_lake_at_rest_with_friction_and_anisotropic_cells():
     h, hu, hv = o.state()
     assert np.abs(hu).max() <= 1e-10 and np.abs(hv).max() <= 1e-10
     assert np.abs(h + sc.b - 1.7).max() <= 1e-11
+
+
+def test_still_sea_at_the_datum_next_to_dry_land_stays_at_rest():
+    # sea at rest at the datum against a beach with hills and a dry curved
+    # island (reading R2: the bed relative to the datum).  The state is the
+    # exact solution: L(u) vanishes exactly, and over 200 steps the state
+    # moves only by the rounding of the RK weights 3/4 and 1/3 (observed
+    # 6e-15 m, momentum 4e-14 m^2/s): no water appears on land, the runup
+    # stays 0 and nothing of note is clamped.
+    sc = inputs.still_coast(dtype=F64)
+    o = oracle.Oracle.from_scenario(sc)
+    land = sc.b > 0
+    assert land.sum() > 0.3 * sc.b.size  # a third of the grid is dry land
+    assert all(not a.any() for a in o.rhs())
+    m0 = o.scalars()["mass"]
+    for _ in range(4):
+        assert o.step(50) == 0
+        h, hu, hv = o.state()
+        assert np.abs(h - sc.h).max() <= 1e-13 and h[land].max() <= 1e-13
+        assert np.abs(hu).max() <= 1e-12 and np.abs(hv).max() <= 1e-12
+        s = o.scalars()
+        assert s["runup"] == 0.0 and s["clamp_mass"] <= 1e-14 * m0
+        assert abs(s["mass"] - m0) <= 1e-13 * m0
+
+
+def test_still_sea_at_the_datum_with_a_wave_keeps_the_land_dry_ahead_of_it():
+    # the same coast with a wave far offshore: until the wave arrives the
+    # land ahead of it stays dry and the momentum there stays zero
+    sc = inputs.still_coast(dtype=F64)
+    X = (np.arange(sc.params.nx) + 0.5) * sc.params.dx
+    hump = 0.2 * np.exp(-((X - 10.0) / 5.0) ** 2)
+    h = np.where(sc.b < 0, np.maximum(hump - sc.b, 0.0), 0.0)
+    o = oracle.Oracle(sc.params, sc.b, sc.n, h, sc.hu, sc.hv)
+    assert o.step(10) == 0
+    h1, hu1, _ = o.state()
+    far = X > 0.5 * sc.params.nx * sc.params.dx  # beyond the island
+    assert np.abs(h1[:, far] - h[:, far]).max() <= 1e-13
+    assert np.abs(hu1[:, far]).max() <= 1e-12
+    assert o.scalars()["runup"] == 0.0
 
 
 # ---------------------------------------------------------------------------
@@ -367,6 +418,28 @@ def test_implicit_friction_keeps_the_steady_slope():
     assert np.abs(h - sc.h).max() < 1e-12
     assert np.abs(hu - sc.hu).max() < 1e-11
     assert np.abs(hv).max() == 0.0
+
+
+def test_friction_cap_cuts_a_stiff_rate_to_one_over_dt():
+    # Manning n = 10 on a 5 cm film with kappa_cap = 1 (reading R8): kappa dt
+    # is ~2.7e4 at the start, above the cap 1/dt at every stage that sees
+    # flow.  Mid-channel only friction acts, so stage 1 removes the whole
+    # discharge (q1 = q - dt (1/dt) q = 0), stage 2 sees no flow and keeps
+    # 3/4 q^n, stage 3 removes its input's discharge again and ends at
+    # (1/3) q^n: the discharge falls by exactly a factor 3 per step while
+    # the depth stays.
+    sc = inputs.friction_channel(manning=10.0, dt_fixed=0.5, kappa_cap=1.0, dtype=F64)
+    mid = sc.params.nx // 2
+    o = oracle.Oracle.from_scenario(sc)
+    (h1, hu1, _), dt = o.stage1()
+    assert dt == 0.5 and hu1[1, mid] == 0.0 and h1[1, mid] == sc.meta["depth"]
+    q = sc.meta["q0"]
+    for _ in range(6):
+        assert o.step(1) == 0
+        h, hu, hv = o.state()
+        q = q / 3.0
+        assert abs(hu[1, mid] - q) <= 1e-14 * q
+        assert h[1, mid] == sc.meta["depth"] and hv[1, mid] == 0.0
 
 
 def test_implicit_friction_without_manning_is_the_explicit_scheme():
