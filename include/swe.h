@@ -6,11 +6,16 @@
  * form u_t + F_x + G_y = S of Eq. (4) with u = (h, hu, hv):
  *   - fifth-order WENO reconstruction at every half-step face (Methods, WENO
  *     paragraph) of the Lax-Friedrichs split fluxes F+- = (F +- alpha u~)/2,
- *     u~ = (h + b, hu, hv), with alpha the global maximum characteristic
+ *     u~ = (h + m, hu, hv), with alpha the global maximum characteristic
  *     speed of each RK stage (Methods, Lax-Friedrichs paragraph, Eq. (6));
- *   - the bed source -g (h + b) grad b, centred at the cell, its face values
- *     of b reconstructed with the normal-momentum flux's WENO weights, and the
- *     explicit Manning friction -g n^2 |q| q / h^(7/3) (Eqs. (2)-(3), (7));
+ *   - the pressure flux 1/2 g (h^2 - m^2) and the bed source
+ *     -g (h + m) grad b, centred at the cell, its face values of b
+ *     reconstructed with the normal-momentum flux's WENO weights, and the
+ *     explicit Manning friction -g n^2 |q| q / h^(7/3) (Eqs. (2)-(3), (7)).
+ *     m = min(b, 0) takes the bed relative to the datum (the still-water
+ *     level 0): below it this is the printed form with b, and on land
+ *     (m = 0) the depth form 1/2 g h^2, -g h grad b, under which dry land
+ *     carries no flux and still water at the datum stays at rest exactly;
  *   - the three-stage TVD Runge-Kutta update of Eq. (8).
  * Options (off by default): point-implicit friction in place of the explicit
  * term (SWE_OPT_FRICTION_IMPLICIT) and a compensated FP32 level

@@ -4,7 +4,7 @@
 // every cell of a TX x TY tile, where L is the explicit operator of Eq. (7):
 // the divergence of WENO5-reconstructed Lax-Friedrichs split fluxes
 // (Methods, WENO and Lax-Friedrichs paragraphs) plus the cell-centred bed and
-// Manning sources of Eqs. (2)-(3).
+// Manning sources of Eqs. (2)-(3), with the bed taken relative to the datum.
 //
 // Work layout, per block:
 //   1. the tile's input state (s, hu, hv, b) with a 3-cell cross-shaped halo
@@ -160,7 +160,7 @@ __device__ __forceinline__ float wt(float beta12, float kd, float ek)
 // of the window cell 3 before the first cell, st the LDS step between cells.
 // emit(k, L0, L1, L2) receives, as soon as cell k's second face completes,
 // the sweep's part of L for that cell: -(Fhat_{k+1/2} - Fhat_{k-1/2})/ds, plus
-// the bed term -g (h+b)(bhat_{k+1/2} - bhat_{k-1/2})/ds on the momentum
+// the bed term -g (h + min(b, 0))(bhat_{k+1/2} - bhat_{k-1/2})/ds on the momentum
 // component normal to the faces.
 template <int R, int DIR, class Emit>
 __device__ __forceinline__ void sweep(const float *__restrict__ Ls, const float *__restrict__ Lhu,
@@ -190,12 +190,16 @@ __device__ __forceinline__ void sweep(const float *__restrict__ Ls, const float 
     for (int w = -HALO; w < R + HALO; ++w) {
         const int li = li0 + (w + HALO) * st;
         const float sv = Ls[li], hu = Lhu[li], hv = Lhv[li], b = Lb[li];
-        // depth and surface elevation from the stored level (see Geo)
-        const float h = sv - fminf(b, 0.f);
-        const float e = sv + fmaxf(b, 0.f);
-        // cell flux, LF split vector u~ = (h+b, hu, hv) and the split fluxes
+        // the bed enters relative to the datum: lo = min(b, 0), the level of
+        // zero depth below it.  The stored level is sv = h + lo (see Geo), the
+        // pressure 1/2 g (h^2 - lo^2) = 1/2 g (h - lo) sv, the LF split vector
+        // u~ = (sv, hu, hv) and the bed term's coefficient sv: the printed
+        // (h + b) form below the datum, the depth form on land, where dry
+        // cells then carry no flux at all
+        const float lo = fminf(b, 0.f);
+        const float h = sv - lo;
         const float inv = h > K.h_dry ? frcp(h) : 0.f;
-        const float pres = K.half_g * (h - b) * e;
+        const float pres = K.half_g * (h - lo) * sv;
         float F0, F1, F2;
         if (DIR == 0) {
             F0 = hu;
@@ -211,14 +215,14 @@ __device__ __forceinline__ void sweep(const float *__restrict__ Ls, const float 
             win[0][q] = win[1][q];
             win[1][q] = win[2][q];
         }
-        win[2][0] = fmaf(K.a, e, F0);
+        win[2][0] = fmaf(K.a, sv, F0);
         win[2][1] = fmaf(K.a, hu, F1);
         win[2][2] = fmaf(K.a, hv, F2);
-        win[2][3] = fmaf(-K.a, e, F0);
+        win[2][3] = fmaf(-K.a, sv, F0);
         win[2][4] = fmaf(-K.a, hu, F1);
         win[2][5] = fmaf(-K.a, hv, F2);
         win[2][6] = b;
-        if (w >= 0 && w < R) eta[w >= 0 && w < R ? w : 0] = e;
+        if (w >= 0 && w < R) eta[w >= 0 && w < R ? w : 0] = sv;
         if (w < -1) continue;
 
         const int c = w - 1;  // cell centre whose three cells are now in the window

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from parity import TOL_SHOCK, TOL_SMOOTH, field_errors, front_split_errors
+from parity import TOL_SHOCK, TOL_SMOOTH, assert_epilogue_parity, assert_front_parity, field_errors
 from paper_2301_12010_amd import inputs, swe
 
 pytestmark = pytest.mark.gpu
@@ -86,9 +86,8 @@ def test_batch_against_checker():
         g = bt.read(i)
         o = oracle.Oracle.from_scenario(sc)
         o.step(n)
-        e_h, e_hu, e_hv, dm, _ = front_split_errors(g, o.state())
-        say(sc.name, n, e_h, e_hu, e_hv, dm)
-        assert max(e_h, e_hu, e_hv) <= TOL_SHOCK and dm <= 5e-3
+        assert_front_parity(g, o.state(), TOL_SHOCK, f"{sc.name} {n}")
+        assert_epilogue_parity(g[3], o.scalars(), sc, sc.name)
     bt.close()
 
 
@@ -112,9 +111,8 @@ def test_mitigation_ensemble_full_size_truncated():
         if i < 3:
             o = oracle.Oracle.from_scenario(sc)
             o.step(n)
-            e_h, e_hu, e_hv, dm, frac = front_split_errors(g, o.state())
-            say("ensemble member", i, e_h, e_hu, e_hv, dm, frac)
-            assert max(e_h, e_hu, e_hv) <= TOL_SHOCK and dm <= 5e-3
+            assert_front_parity(g, o.state(), TOL_SHOCK, f"ensemble member {i}")
+            assert_epilogue_parity(g[3], o.scalars(), sc, f"ensemble member {i}")
     bt.close()
 
 
@@ -140,9 +138,9 @@ def test_uneven_batch_full_sizes_truncated():
     for i, (sc, n) in enumerate(zip(scen, steps)):
         o = oracle.Oracle.from_scenario(sc)
         assert o.step(n) == 0
-        e = front_split_errors(bt.read(i), o.state())
-        say("uneven", sc.name, e)
-        assert max(e[:3]) <= TOL_SHOCK and e[3] <= 5e-3
+        g = bt.read(i)
+        assert_front_parity(g, o.state(), TOL_SHOCK, f"uneven {sc.name}")
+        assert_epilogue_parity(g[3], o.scalars(), sc, f"uneven {sc.name}")
     bt.close()
 
 
@@ -161,7 +159,6 @@ def test_nwave_beach_with_hill_against_checker():
         assert np.array_equal(a, b)
     o = oracle.Oracle.from_scenario(sc)
     o.step(40)
-    e_h, e_hu, e_hv, dm, frac = front_split_errors(g, o.state())
-    say("nwave", e_h, e_hu, e_hv, dm, frac, g[3]["runup"], o.scalars()["runup"])
-    assert max(e_h, e_hu, e_hv) <= TOL_SHOCK and dm <= 5e-3
+    assert_front_parity(g, o.state(), TOL_SHOCK, "nwave")
+    assert_epilogue_parity(g[3], o.scalars(), sc, "nwave")
     bt.close()

@@ -19,7 +19,7 @@ import numpy as np
 import pytest
 
 import oracle
-from parity import TOL_SMOOTH, front_split_errors
+from parity import TOL_SMOOTH, assert_epilogue_parity, assert_front_parity
 from paper_2301_12010_amd import inputs, swe
 
 pytestmark = pytest.mark.gpu
@@ -53,11 +53,10 @@ def test_large_coast_first_steps_against_checker(coast):
         if k % 5 == 4:
             say("checker step", k + 1)
     ref = o.state()
-    e_h, e_hu, e_hv, dm, frac = front_split_errors(g, ref)
-    say("full-size errors", e_h, e_hu, e_hv, "front band", dm, frac)
-    assert max(e_h, e_hu, e_hv) <= TOL_SMOOTH and dm <= 5e-3
+    assert_front_parity(g, ref, TOL_SMOOTH, "coast 4096^2, 20 steps")
     rs = o.scalars()
     assert abs(g[3]["t"] - rs["t"]) <= 1e-6 * rs["t"]
+    assert_epilogue_parity(g[3], rs, coast, "coast 4096^2, 20 steps")
 
 
 @pytest.mark.parametrize("implicit,compensated", [(1, 0), (0, 1)])
@@ -79,9 +78,8 @@ def test_large_coast_first_steps_with_options(coast, implicit, compensated):
     o = oracle.Oracle.from_scenario(coast)
     o.set_friction(bool(implicit))
     assert o.step(n) == 0
-    e_h, e_hu, e_hv, dm, frac = front_split_errors(g, o.state())
-    say("full-size errors", e_h, e_hu, e_hv, "front band", dm, frac)
-    assert max(e_h, e_hu, e_hv) <= TOL_SMOOTH and dm <= 5e-3
+    assert_front_parity(g, o.state(), TOL_SMOOTH, f"coast 4096^2 implicit {implicit} compensated {compensated}")
+    assert_epilogue_parity(g[3], o.scalars(), coast, "coast 4096^2 with options")
 
 
 def test_large_coast_properties_over_the_full_run(coast):

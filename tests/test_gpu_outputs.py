@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from parity import TOL_SHOCK, front_split_errors, rel_l2
+from parity import TOL_SHOCK, assert_front_parity, rel_l2
 from paper_2301_12010_amd import inputs, swe
 
 pytestmark = pytest.mark.gpu
@@ -60,9 +60,7 @@ def test_outputs_and_max_depth_against_checker():
         g, r = got[k], ref[k]
         assert g[4] == r[4], (k, g[4], r[4])
         assert abs(g[3] - r[3]) <= 1e-6 * r[3]
-        e_h, e_hu, e_hv, dm, frac = front_split_errors(g, r)
-        say("output", k, "step", g[4], e_h, e_hu, e_hv, dm, frac)
-        assert max(e_h, e_hu, e_hv) <= TOL_SHOCK and dm <= 5e-3
+        assert_front_parity(g, r, TOL_SHOCK, f"output {k} step {g[4]}")
     assert all(np.array_equal(a, b) for a, b in zip(got[1][:3], got[2][:3]))
     e = rel_l2(hmax, ref_hmax)
     say("max depth", e, float(np.abs(hmax - ref_hmax).max()))
