@@ -99,7 +99,7 @@ struct Request {
     int nsteps = 0;
     int status = SWE_PENDING;
     int error = SWE_OK;
-    bool cancel = false;
+    std::atomic<bool> cancel{false};  // set by swe_cancel, read by the server thread
     bool track_max = false;  // keep the maximum-depth map (SWE_SUBMIT_MAX_DEPTH)
     double t_submit = 0, t_admit = 0, t_done = 0;
     // resident state
