@@ -17,10 +17,12 @@
 //      four stencil polynomials are computed once and shared by the three
 //      faces that use them; a face's WENO sums complete two centres later.
 //      The x part of L goes to LDS;
-//   3. y sweep: the same along columns, then friction, the RK combination,
-//      the wet/dry fix-up, the store, and the epilogue reductions (wave
-//      shuffles -> LDS -> at most one atomic per block and quantity) of the
-//      next stage's wave speeds, the clamped mass and the runup.  The FP64
+//   3. y sweep: the same along columns; as soon as a cell's y part of L is
+//      complete, its friction, RK combination, wet/dry fix-up and store
+//      follow (no per-cell results wait in registers), then the epilogue
+//      reductions (wave shuffles -> LDS -> at most one atomic per block and
+//      quantity) of the next stage's wave speeds, the clamped mass and the
+//      runup.  The FP64
 //      mass is not on the step path: a separate deterministic reduction
 //      computes it when the state is read.
 // The arithmetic of a cell does not depend on the tile shape or on which
@@ -573,32 +575,26 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
             }
         }
     }
-    float res[R][3];
     K.a = sc.ay;
     K.hinv_ds = 0.5f * G.inv_dy;
     K.ghinv_ds = -G.g * K.hinv_ds;
-    sweep<R, 1>(Ls, Lhu, Lhv, Lb, (seg * R) * C::SX + col + HALO, C::SX, K,
-                [&](int k, float l0, float l1, float l2) {
-                    res[k][0] = l0;
-                    res[k][1] = l1;
-                    res[k][2] = l2;
-                });
-
     const float h_dry = G.h_dry, dt = sc.dt;
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
+    // cell k of the thread's column segment, as soon as the y sweep has its
+    // part of L (ry0..2): friction, RK combination, fix-up, store, partials.
+    // Done inside the sweep, so no per-cell results wait in registers.
+    auto cell = [&](int k, float ry0, float ry1, float ry2) {
         const int ly = seg * R + k;
         const int gy = y0 + ly;
-        if (gx >= nx || gy >= ny) continue;
+        if (gx >= nx || gy >= ny) return;
         const unsigned gi = (unsigned)(gy * pitch + gx);
         const int li = (ly + HALO) * C::SX + col + HALO;
         const int xi = ly * C::XR + col;
         const float sv = Ls[li], hu = Lhu[li], hv = Lhv[li], bb = Lb[li];
         const float lo = fminf(bb, 0.f);  // level of zero depth
         const float h = sv - lo;
-        float Lh_ = Xr[xi] + res[k][0];
-        float Lhu_ = Xr[C::XPLANE + xi] + res[k][1];
-        float Lhv_ = Xr[2 * C::XPLANE + xi] + res[k][2];
+        float Lh_ = Xr[xi] + ry0;
+        float Lhu_ = Xr[C::XPLANE + xi] + ry1;
+        float Lhv_ = Xr[2 * C::XPLANE + xi] + ry2;
         // explicit Manning friction, wet cells only, rate capped at kappa_cap/dt
         // (IMP: the uncapped rate, taken after the combination)
         const float gn2 = PF ? pgn2[k] : pld(G.gn2, gi);
@@ -713,7 +709,8 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
                 acc.rub = u > acc.rub ? u : acc.rub;
             }
         }
-    }
+    };
+    sweep<R, 1>(Ls, Lhu, Lhv, Lb, (seg * R) * C::SX + col + HALO, C::SX, K, cell);
 }
 
 // Block reduction of the partials and the stage's atomics.  `first` marks
