@@ -200,6 +200,37 @@ int swe_track_max_depth(swe_ctx *ctx, int32_t enable);
  * SWE_EINVAL if the map is not being kept or hmax is NULL. */
 int swe_read_max_depth(swe_ctx *ctx, float *hmax);
 
+/* ---- the same run without allocation -------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * swe_run_noalloc computes what swe_create + swe_step(nsteps) + swe_read
+ * compute for one scenario (bitwise the same state and diagnostics; the
+ * tile variant is the automatic one), but on the caller's device arrays and
+ * without any allocation: the scenario's working storage (swe_footprint
+ * bytes) is a fixed device array of the library, SWE_NOALLOC_MAX_BYTES long,
+ * that every GPU the library runs on holds until the process ends.
+ *   b, manning_n: bed and Manning n, [ny][nx] float32 device arrays (read).
+ *   h, hu, hv: the initial state on entry, the state after nsteps steps on
+ *     return, [ny][nx] float32 device arrays, advanced in place; time starts
+ *     at 0 and the FIXED ghosts are frozen at the entry state.
+ *   hip_stream: the hipStream_t every kernel is enqueued on (NULL: the null
+ *     stream).
+ *   stats: NULL makes the call asynchronous: kernels only, no copy, no
+ *     synchronisation, so it can be captured into a graph and replayed.
+ *     Non-NULL waits for the stream and fills the diagnostics of swe_read.
+ * Errors: SWE_EINVAL for invalid parameters (as swe_create), nsteps < 0, a
+ * NULL or non-device array, a scenario whose footprint exceeds
+ * SWE_NOALLOC_MAX_BYTES (about 1.5 million cells: 1024 x 1024 fits), or,
+ * with stats, input fields that are non-finite or have h < 0 or n < 0 (the
+ * arrays then hold no meaningful state); SWE_EDEVICE for a failed runtime
+ * call; with stats, SWE_ENONFINITE as swe_read.  All calls on one GPU share
+ * its array and each leaves its contents behind: calls that overlap on one
+ * GPU (on different streams or host threads) race and must be serialised by
+ * the caller. */
+#define SWE_NOALLOC_MAX_BYTES (64ull << 20)
+int swe_run_noalloc(const swe_params *p, const float *b, const float *manning_n, float *h,
+                    float *hu, float *hv, int32_t nsteps, void *hip_stream, swe_stats *stats);
+
 /* ---- tile variants and autotuning --------------------------------------- */
 /* Tile variants of the stage kernel: tile width tx, height ty, cells per
  * thread along a sweep r, threads per block. Results are bitwise identical

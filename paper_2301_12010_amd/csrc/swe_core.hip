@@ -341,15 +341,11 @@ size_t scenario_bytes(int nx, int ny)
     return 11 * plane + ghost + align256(sizeof(DevScen)) + align256(MASS_BLOCKS * sizeof(double));
 }
 
-int scenario_upload_into(void *mem, const swe_params &p, const HostFields &f, hipStream_t stream,
-                         DevScenario &d)
+void geo_layout(void *mem, const swe_params &p, Geo &g)
 {
     const int nx = p.nx, ny = p.ny, pitch = plane_pitch(nx);
     const size_t plane = align256((size_t)pitch * ny * sizeof(float));
     char *base = static_cast<char *>(mem);
-    d.base = mem;
-    d.bytes = scenario_bytes(nx, ny);
-    Geo &g = d.geo;
     g.nx = nx;
     g.ny = ny;
     g.pitch = pitch;
@@ -382,6 +378,21 @@ int scenario_upload_into(void *mem, const swe_params &p, const HostFields &f, hi
     g.mass_part = reinterpret_cast<double *>(base + 11 * plane + ghost_b + align256(sizeof(DevScen)));
     g.hmax = nullptr;
     for (int c = 0; c < 3; ++c) g.Rl[c] = nullptr;
+}
+
+int scenario_upload_into(void *mem, const swe_params &p, const HostFields &f, hipStream_t stream,
+                         DevScenario &d)
+{
+    const int nx = p.nx, ny = p.ny, pitch = plane_pitch(nx);
+    const size_t plane = align256((size_t)pitch * ny * sizeof(float));
+    char *base = static_cast<char *>(mem);
+    d.base = mem;
+    d.bytes = scenario_bytes(nx, ny);
+    Geo &g = d.geo;
+    geo_layout(mem, p, g);
+    float *planes[11];
+    for (int k = 0; k < 11; ++k) planes[k] = reinterpret_cast<float *>(base + k * plane);
+    float *ghost = reinterpret_cast<float *>(base + 11 * plane);
 
     const size_t N = (size_t)nx * ny;
     std::vector<float> gn2(N), s0(N);

@@ -54,6 +54,10 @@ struct DevScenario {
 };
 
 size_t scenario_bytes(int nx, int ny);
+// Geometry, parameters and plane addresses of a scenario stored in `mem`
+// (scenario_bytes() of it, 256-byte aligned): 11 planes, FIXED ghosts,
+// DevScen, mass partials.  Fills g only; touches no memory.
+void geo_layout(void *mem, const swe_params &p, Geo &g);
 
 // Allocates (dev_alloc) and uploads on `stream`, then runs the init kernel.
 int scenario_upload(const swe_params &p, const HostFields &f, hipStream_t stream, DevScenario &d);

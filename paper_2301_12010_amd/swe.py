@@ -21,6 +21,7 @@ OPT_GRAPH_STEPS, OPT_TILE, OPT_COMPENSATED, OPT_FRICTION_IMPLICIT = 1, 2, 3, 4
 BATCH_PERSISTENT, BATCH_ROUNDS = 0, 1
 PENDING, DONE, FAILED, CANCELLED = 0, 1, 2, 3
 SUBMIT_MAX_DEPTH = 1
+NOALLOC_MAX_BYTES = 64 << 20  # SWE_NOALLOC_MAX_BYTES: working array of swe_run_noalloc
 
 
 class SweError(RuntimeError):
@@ -123,6 +124,8 @@ _SIGS = {
     "swe_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "swe_footprint": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "swe_set_allocator": (ctypes.c_int, [ALLOC_FN, RELEASE_FN, _VP]),
+    "swe_run_noalloc": (ctypes.c_int, [ctypes.POINTER(Params), _FP, _FP, _FP, _FP, _FP, ctypes.c_int32,
+                                       _VP, ctypes.POINTER(Stats)]),
 }
 
 _LIB = None
@@ -202,6 +205,22 @@ def _stream_handle(stream):
     if hasattr(stream, "cuda_stream"):
         return stream.cuda_stream
     return int(stream)
+
+
+def run_noalloc(params, b, n, h, hu, hv, nsteps: int, stream=None, stats: bool = True):
+    """swe_run_noalloc: advance the device arrays (h, hu, hv) in place by
+    nsteps steps, with no device allocation (the library's fixed working
+    array).  Inputs are contiguous float32 (ny, nx) device tensors.  With
+    stats the call waits and returns the diagnostics as a dict; without, it
+    only enqueues kernels on `stream` and returns None."""
+    q = make_params(params)
+    keep = []
+    ptrs = [_ptr(a, q.ny, q.nx, keep) for a in (b, n, h, hu, hv)]
+    st = Stats() if stats else None
+    rc = _lib().swe_run_noalloc(ctypes.byref(q), *ptrs, int(nsteps), _stream_handle(stream),
+                                ctypes.byref(st) if st is not None else None)
+    _check(rc, "swe_run_noalloc")
+    return st.as_dict() if st is not None else None
 
 
 class Solver:
