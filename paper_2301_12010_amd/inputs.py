@@ -15,7 +15,8 @@ Workloads follow the paper's verification and validation problems:
   bed source term the Methods section takes from Xing & Shu);
 * synthetic coastlines standing in for the paper's beach/hill and Crescent
   City runs (Sections 2.4-2.5): a linear beach, Gaussian bumps and hills,
-  Manning-n patches and a Gaussian free-surface hump.
+  Manning-n patches, and a Gaussian free-surface hump (the large coastline)
+  or Carrier's N-wave (the mitigation ensemble and the uneven batch).
 
 Arrays are row-major ``[ny][nx]`` with x fastest; cell centres sit at
 ``x_i = (i + 1/2) dx``, ``y_j = (j + 1/2) dy``.
@@ -347,13 +348,19 @@ def deep_ocean(nx: int = 96, ny: int = 64, dx: float = 1000.0, seed: int = 5,
 
 def mitigation_coast(nx: int = 1024, ny: int = 1024, dx: float = 2.0, seed: int = 1000,
                      nsteps: int = 3000) -> Scenario:
-    """One mitigation-ensemble member: beach + coastal hills + Manning patches.
+    """One mitigation-ensemble member: Carrier's N-wave running up a beach
+    with coastal hills and Manning patches (the hill-on-a-beach study of
+    Section 2.4 as a mitigation ensemble).
 
-    1-8 hills of height U(3, 10) m and radius U(20, 80) m centred at
-    x ~ U(xs - 50, xs + 150), y ~ U(0, Ly); background n = 0.025 with 1-4
-    disks of radius U(50, 200) m and n ~ U(0.02, 0.1) (later disks win),
-    disk centres x ~ U(xs - 200, Lx), y ~ U(0, Ly); a 2 m Gaussian plane
-    hump of radius 100 m centred 300 m offshore of the shoreline xs.
+    Beach as ``_beach`` (shoreline xs = 0.8 Lx, slope 1/200); 1-8 hills of
+    height U(3, 10) m and radius U(20, 80) m centred at x ~ U(xs - 50,
+    xs + 150), y ~ U(0, Ly); background n = 0.025 with 1-4 disks of radius
+    U(50, 200) m and n ~ U(0.02, 0.1) (later disks win), disk centres
+    x ~ U(xs - 200, Lx), y ~ U(0, Ly).  The initial surface is the N-wave of
+    ``nwave_surface`` scaled to the grid: A = 1 m (a 2 m crest and a 0.67 m
+    leading trough), lambda = 0.2 Lx and the origin 0.05 Lx offshore, so on
+    a 1024 x 1024 grid of 2 m cells the crest stands 313 m offshore; water
+    at rest, free-slip walls.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     X, Y = _centres(nx, ny, dx, dx)
@@ -370,7 +377,7 @@ def mitigation_coast(nx: int = 1024, ny: int = 1024, dx: float = 2.0, seed: int 
         cx, cy = rng.uniform(xs - 200.0, Lx), rng.uniform(0, Ly)
         nv = rng.uniform(0.02, 0.1)
         n = np.where((X - cx) ** 2 + (Y - cy) ** 2 <= R * R, nv, n)
-    eta = 2.0 * np.exp(-((X - (xs - 300.0)) / 100.0) ** 2)
+    eta = nwave_surface(xs - X, A=1.0, lam=0.2 * Lx, origin=0.05 * Lx)
     h, hu, hv = _wet_state(eta, b, 1e-3)
     p = Params(nx, ny, dx, dx, cfl=0.4, h_dry=1e-3, kappa_cap=1.0)
     return Scenario(f"mitigation_{nx}x{ny}_s{seed}", p, _f32(b), _f32(n), _f32(h),
