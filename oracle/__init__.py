@@ -84,6 +84,8 @@ def _declare(L):
     L.oracle_num_threads.argtypes = []
     L.oracle_set_friction.restype = None
     L.oracle_set_friction.argtypes = [P, ctypes.c_int]
+    L.oracle_set_split.restype = None
+    L.oracle_set_split.argtypes = [P, ctypes.c_int]
 
 
 def _dp(a: np.ndarray):
@@ -139,6 +141,10 @@ class Oracle:
     def set_friction(self, implicit: bool):
         """Point-implicit friction per stage (reading R10) or the explicit term."""
         self._L.oracle_set_friction(self._ptr, 1 if implicit else 0)
+
+    def set_split(self, local: bool):
+        """Local Lax-Friedrichs splitting per face (reading R11) or the global speed."""
+        self._L.oracle_set_split(self._ptr, 1 if local else 0)
 
     def state(self):
         h = np.empty((self.ny, self.nx))

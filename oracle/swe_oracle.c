@@ -65,6 +65,14 @@
  *         q_out = [a_n q^n + a_w (q_w + dt L'(w))] / (1 + a_w dt kappa(w)),
  *       L' the right-hand side without friction, (a_n, a_w) = (0, 1),
  *       (3/4, 1/4), (1/3, 2/3) for the three stages.
+ *   R11 Variant, off by default (oracle_set_split): local Lax-Friedrichs
+ *       splitting.  The paper splits with one global maximum speed per
+ *       stage (Methods, Lax-Friedrichs paragraph); this variant takes, for
+ *       each face, the largest normal speed |u_n| + sqrt(g h+) over the six
+ *       cells that the face's two reconstructions read, and splits those six
+ *       cells' fluxes with it.  Each face flux stays single-valued
+ *       (conservative), and a constant h + m gives no mass flux
+ *       (well-balanced as R2).  The time step stays global (R4).
  *
  * Build: gcc -O2 -std=c11 -fopenmp -ffp-contract=off -fPIC -shared.
  */
@@ -104,6 +112,7 @@ typedef struct {
     int64_t step;
     int nonfinite;
     int friction_implicit;        /* R10 */
+    int local_alpha;              /* R11 */
 } oracle_ctx;
 
 static inline size_t IX(const oracle_ctx *c, int i, int j)
@@ -322,33 +331,50 @@ static void cell_flux(const oracle_ctx *c, int dir, double h, double hu, double 
     U[2] = hv;
 }
 
+/* Speed of the fastest wave along direction dir in one cell (R3, R11). */
+static double normal_speed(const oracle_ctx *c, int dir, double h, double hu, double hv)
+{
+    const double hp = h > 0.0 ? h : 0.0;
+    double un = 0.0;
+    if (h > c->p.h_dry)
+        un = (dir == 0 ? hu : hv) / h;
+    return fabs(un) + sqrt(c->p.g * hp);
+}
+
 /* One line of faces along direction dir.  n = number of interior cells on the
  * line; val(k) for k in [-3, n+3) reads the extended line.  Outputs
  * div[m][k] = -(Fhat_{k+1/2} - Fhat_{k-1/2}) / ds and dbh[k] = bhat_{k+1/2} - bhat_{k-1/2}
- * for the interior cells k in [0, n). */
+ * for the interior cells k in [0, n).  alpha is the stage's global speed;
+ * with R11 each face takes its own from sp. */
 static void line_faces(const oracle_ctx *c, int dir, int n, double alpha, double ds,
                        const double *lh, const double *lhu, const double *lhv, const double *lb,
                        double *div0, double *div1, double *div2, double *dbh,
-                       double *Fp, double *Fm, double *Fhat, double *bhat)
+                       double *Fc, double *Uc, double *sp, double *Fhat, double *bhat)
 {
-    /* split fluxes at every cell of the extended line: Fp/Fm[(k+3)*3 + m] */
+    /* cell fluxes and LF split vectors at every cell of the extended line:
+     * Fc/Uc[(k+3)*3 + m]; normal wave speeds sp[k+3] for R11 */
     for (int k = -HALO; k < n + HALO; k++) {
-        double F[3], U[3];
-        cell_flux(c, dir, lh[k], lhu[k], lhv[k], lb[k], F, U);
-        for (int m = 0; m < 3; m++) {
-            Fp[(k + HALO) * 3 + m] = 0.5 * (F[m] + alpha * U[m]);
-            Fm[(k + HALO) * 3 + m] = 0.5 * (F[m] - alpha * U[m]);
-        }
+        cell_flux(c, dir, lh[k], lhu[k], lhv[k], lb[k], &Fc[(k + HALO) * 3], &Uc[(k + HALO) * 3]);
+        sp[k + HALO] = normal_speed(c, dir, lh[k], lhu[k], lhv[k]);
     }
     /* the momentum component normal to the faces owns the bed weights */
     const int mb = dir == 0 ? 1 : 2;
     /* face f = k + 1/2 for k in [-1, n): stored at index k + 1 */
     for (int k = -1; k < n; k++) {
+        double a = alpha;
+        if (c->local_alpha) {
+            a = 0.0;
+            for (int s = -2; s <= 3; s++)  /* cells k-2 .. k+3 */
+                if (sp[k + s + HALO] > a)
+                    a = sp[k + s + HALO];
+        }
         double wp[3], wm[3], vp[5], vm[5];
         for (int m = 0; m < 3; m++) {
             for (int s = 0; s < 5; s++) {
-                vp[s] = Fp[(k - 2 + s + HALO) * 3 + m];  /* cells k-2 .. k+2 */
-                vm[s] = Fm[(k + 3 - s + HALO) * 3 + m];  /* cells k+3 .. k-1 */
+                const int ip = (k - 2 + s + HALO) * 3 + m;  /* cells k-2 .. k+2 */
+                const int im = (k + 3 - s + HALO) * 3 + m;  /* cells k+3 .. k-1 */
+                vp[s] = 0.5 * (Fc[ip] + a * Uc[ip]);
+                vm[s] = 0.5 * (Fc[im] - a * Uc[im]);
             }
             double w0[3], w1[3];
             const double rp = weno5(vp, c->p.weno_eps, w0);
@@ -386,8 +412,8 @@ static void rhs(oracle_ctx *c, const double *h, const double *hu, const double *
         const int nmax = (nx > ny ? nx : ny) + 2 * HALO;
         double *lh = malloc(sizeof(double) * nmax * 4);
         double *lhu = lh + nmax, *lhv = lh + 2 * nmax, *lb = lh + 3 * nmax;
-        double *Fp = malloc(sizeof(double) * nmax * 3 * 2);
-        double *Fm = Fp + nmax * 3;
+        double *Fc = malloc(sizeof(double) * nmax * 7);
+        double *Uc = Fc + nmax * 3, *sp = Fc + nmax * 6;
         double *Fhat = malloc(sizeof(double) * (nmax + 1) * 3);
         double *bhat = malloc(sizeof(double) * (nmax + 1));
         double *d0 = malloc(sizeof(double) * nmax * 4);
@@ -401,7 +427,7 @@ static void rhs(oracle_ctx *c, const double *h, const double *hu, const double *
                 lhv[k + HALO] = hv[e]; lb[k + HALO] = c->b[e];
             }
             line_faces(c, 0, nx, ax, c->p.dx, lh + HALO, lhu + HALO, lhv + HALO, lb + HALO,
-                       d0, d1, d2, db, Fp, Fm, Fhat, bhat);
+                       d0, d1, d2, db, Fc, Uc, sp, Fhat, bhat);
             for (int i = 0; i < nx; i++) {
                 const size_t o = II(c, i, j);
                 const double eta = h[IX(c, i, j)] + datum_bed(c->b[IX(c, i, j)]);
@@ -420,7 +446,7 @@ static void rhs(oracle_ctx *c, const double *h, const double *hu, const double *
                 lhv[k + HALO] = hv[e]; lb[k + HALO] = c->b[e];
             }
             line_faces(c, 1, ny, ay, c->p.dy, lh + HALO, lhu + HALO, lhv + HALO, lb + HALO,
-                       d0, d1, d2, db, Fp, Fm, Fhat, bhat);
+                       d0, d1, d2, db, Fc, Uc, sp, Fhat, bhat);
             for (int j = 0; j < ny; j++) {
                 const size_t o = II(c, i, j);
                 const double eta = h[IX(c, i, j)] + datum_bed(c->b[IX(c, i, j)]);
@@ -430,7 +456,7 @@ static void rhs(oracle_ctx *c, const double *h, const double *hu, const double *
                 c->bedy[o] = -g * eta * db[j] / c->p.dy;
             }
         }
-        free(lh); free(Fp); free(Fhat); free(bhat); free(d0);
+        free(lh); free(Fc); free(Fhat); free(bhat); free(d0);
     }
 
     /* sources and assembly: L = ((-dF/dx) + (-dG/dy)) + S */
@@ -665,6 +691,13 @@ int oracle_step(oracle_ctx *c, int nsteps)
         wave_speeds(c, c->h, c->hu, c->hv, &c->alpha_x, &c->alpha_y);
     }
     return c->nonfinite ? -4 : 0;
+}
+
+/* R11: 1 selects local Lax-Friedrichs splitting, 0 (default) the global speed. */
+void oracle_set_split(oracle_ctx *c, int local)
+{
+    if (c)
+        c->local_alpha = local ? 1 : 0;
 }
 
 /* R10: 1 selects point-implicit friction, 0 (default) the explicit term. */

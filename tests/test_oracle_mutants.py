@@ -207,6 +207,27 @@ def cap_flags(L):
     return False
 
 
+def llf_equal_flags(L):
+    # local LF splitting where every face stencil holds the fastest cell:
+    # stage 1 equals the global split bitwise
+    from test_oracle_pins import fastest_every_third_cell
+    a = oracle.Oracle(*fastest_every_third_cell(), L=L)
+    b = oracle.Oracle(*fastest_every_third_cell(), L=L)
+    b.set_split(True)
+    return not all(np.array_equal(x, y) for x, y in zip(a.stage1()[0], b.stage1()[0]))
+
+
+def llf_mirror_flags(L):
+    sc = inputs.random_wet(21, 13, seed=9, dry_fraction=0.05)
+    o1 = oracle.Oracle.from_scenario(sc, L=L)
+    o2 = oracle.Oracle.from_scenario(inputs.mirror_x(sc), L=L)
+    o1.set_split(True)
+    o2.set_split(True)
+    o1.step(5)
+    o2.step(5)
+    return not np.array_equal(o2.state()[0], o1.state()[0][:, ::-1])
+
+
 MUTANTS = [
     # (id, anchor, replacement, detector)
     ("surface_viscosity_on_h", "U[0] = h + m;", "U[0] = h;", lake_flags),
@@ -217,17 +238,22 @@ MUTANTS = [
      "const double eta = h[IX(c, i, j)] + datum_bed(c->b[IX(c, i, j)]);\n                c->fx[0][o]",
      "const double eta = h[IX(c, i, j)] + c->b[IX(c, i, j)];\n                c->fx[0][o]", land_slope_flags),
     ("friction_cap_removed", "if (kappa > cap)\n                    kappa = cap;", "", cap_flags),
+    ("llf_window_of_two_cells", "for (int s = -2; s <= 3; s++)  /* cells k-2 .. k+3 */",
+     "for (int s = 0; s <= 1; s++)  /* cells k-2 .. k+3 */", llf_equal_flags),
+    ("llf_window_not_centred", "for (int s = -2; s <= 3; s++)  /* cells k-2 .. k+3 */",
+     "for (int s = -2; s <= 2; s++)  /* cells k-2 .. k+3 */", llf_mirror_flags),
+    ("llf_speed_tangential", "un = (dir == 0 ? hu : hv) / h;", "un = (dir == 0 ? hv : hu) / h;", llf_equal_flags),
     ("friction_cap_times_dt", "c->p.kappa_cap / dt : INFINITY", "c->p.kappa_cap * dt : INFINITY", cap_flags),
     ("bed_weights_from_mass", "const int mb = dir == 0 ? 1 : 2;", "const int mb = 0;", lake_flags),
     ("bed_y_sign", "c->bedy[o] = -g * eta * db[j] / c->p.dy;",
      "c->bedy[o] = g * eta * db[j] / c->p.dy;", lake_flags),
     ("pressure_drops_bed", "const double pres = 0.5 * c->p.g * (h * h - m * m);",
      "const double pres = 0.5 * c->p.g * h * h;", lake_flags),
-    ("minus_stencil_not_mirrored", "vm[s] = Fm[(k + 3 - s + HALO) * 3 + m];",
-     "vm[s] = Fm[(k - 2 + s + HALO) * 3 + m];", dam_flags),
+    ("minus_stencil_not_mirrored", "const int im = (k + 3 - s + HALO) * 3 + m;",
+     "const int im = (k - 2 + s + HALO) * 3 + m;", dam_flags),
     ("advective_flux_dropped", "F[1] = hu * u + pres;", "F[1] = pres;", dam_flags),
-    ("split_sign", "Fm[(k + HALO) * 3 + m] = 0.5 * (F[m] - alpha * U[m]);",
-     "Fm[(k + HALO) * 3 + m] = 0.5 * (F[m] + alpha * U[m]);", dam_flags),
+    ("split_sign", "vm[s] = 0.5 * (Fc[im] - a * Uc[im]);",
+     "vm[s] = 0.5 * (Fc[im] + a * Uc[im]);", dam_flags),
     ("rk_stage2_weights", "combine(c, 0.75, 0.25,", "combine(c, 0.5, 0.5,", order_flags),
     ("rk_stage3_weights", "combine(c, 1.0 / 3.0, 2.0 / 3.0,", "combine(c, 0.5, 0.5,", order_flags),
     ("friction_exponent", "pow(h[e], 7.0 / 3.0)", "pow(h[e], 4.0 / 3.0)", slope_flags),

@@ -508,3 +508,100 @@ def test_runup_is_the_highest_wet_bed_reached():
         best = max(best, highest_wet_bed(o.state()[0]))
         assert o.scalars()["runup"] == best
     assert best > highest_wet_bed(h)  # the wave climbed the beach
+
+
+# ---------------------------------------------------------------------------
+# Local Lax-Friedrichs splitting, the variant of the Methods' global speed
+# (reading R11 of the checker: each face splits the six cells its two
+# reconstructions read with the largest normal speed among them)
+# ---------------------------------------------------------------------------
+
+def fastest_every_third_cell():
+    """A y-uniform state whose x speed peaks at every third cell: every
+    face's six-cell stencil (ghosts included) holds the fastest cell."""
+    nx, ny = 60, 5
+    i = np.arange(nx)
+    hu = np.tile(np.where(i % 3 == 0, 0.5, 0.1), (ny, 1))
+    z = np.zeros((ny, nx))
+    return inputs.Params(nx, ny, 1.0, 1.0, cfl=0.4), np.full((ny, nx), -2.0), z, np.ones((ny, nx)), hu, z
+
+
+def test_local_lf_is_the_global_split_where_every_stencil_holds_the_fastest_cell():
+    a = oracle.Oracle(*fastest_every_third_cell())
+    b = oracle.Oracle(*fastest_every_third_cell())
+    b.set_split(True)
+    (ga, dta), (gb, dtb) = a.stage1(), b.stage1()
+    assert dta == dtb
+    assert all(np.array_equal(x, y) for x, y in zip(ga, gb))
+    assert np.abs(ga[1] - fastest_every_third_cell()[4]).max() > 1e-3  # the stage did change hu
+
+
+def test_local_lf_keeps_still_water_at_rest():
+    sc = inputs.lake_at_rest(dtype=F64)
+    o = oracle.Oracle.from_scenario(sc)
+    o.set_split(True)
+    assert o.step(1000) == 0
+    h, hu, hv = o.state()
+    assert np.abs(hu).max() <= 1e-10 and np.abs(hv).max() <= 1e-10
+    assert np.abs(h + sc.b - 1.7).max() <= 1e-11
+    sc = inputs.still_coast(dtype=F64)
+    o = oracle.Oracle.from_scenario(sc)
+    o.set_split(True)
+    assert o.step(200) == 0
+    h, hu, _ = o.state()
+    assert np.abs(h - sc.h).max() <= 1e-13 and np.abs(hu).max() <= 1e-12
+    assert o.scalars()["runup"] == 0.0
+
+
+def test_local_lf_dam_break_against_stoker():
+    sc = inputs.dam_break()
+    o = oracle.Oracle.from_scenario(sc)
+    o.set_split(True)
+    assert o.step(sc.nsteps) == 0
+    s = o.scalars()
+    h = o.state()[0]
+    x = (np.arange(sc.params.nx) + 0.5) * sc.params.dx
+    ha = A.dam_break_h(x, s["t"], 2.0, 1.0, 64.0)
+    x1, x2, x3, _ = A.dam_break_fronts(s["t"], 2.0, 1.0, 64.0)
+    away = (np.abs(x - x1) > 3) & (np.abs(x - x2) > 3) & (np.abs(x - x3) > 3)
+    assert A.rel_l2(h[31], ha) < 2.0e-2 and A.rel_l2(h[31][away], ha[away]) < 2.5e-3
+    assert np.array_equal(h, np.broadcast_to(h[0], h.shape))
+
+
+def test_local_lf_bowl_fronts_are_less_diffused():
+    # small speeds near the wet/dry fronts give a smaller local viscosity:
+    # the bowl's error falls 4x against the global speed (2.0e-3 -> 5.3e-4 at
+    # dx = 1) and still falls with dx
+    h0, a, L, amp = 1.0, 200.0, 600.0, 20.0
+    T = 2 * np.pi / A.bowl_omega(h0, a)
+    errs = {}
+    for local in (False, True):
+        for nx, dx in [(300, 2.0), (600, 1.0)]:
+            sc = inputs.parabolic_bowl(nx=nx, ny=3, dx=dx, dtype=F64)
+            o = oracle.Oracle.from_scenario(sc)
+            o.set_split(local)
+            s = run_to(o, 0.3 * T)
+            x = (np.arange(nx) + 0.5) * dx
+            errs[local, dx] = A.rel_l2(o.state()[0][1], A.bowl_h(x, s["t"], h0, a, L, amp))
+            m0 = float(np.sum(sc.h)) * dx * dx
+            assert abs(s["mass"] - m0 - s["clamp_mass"]) <= 1e-12 * m0
+    assert errs[True, 1.0] < 0.5 * errs[False, 1.0]
+    assert errs[True, 1.0] < errs[True, 2.0]
+
+
+def test_local_lf_symmetries_and_walls():
+    sc = inputs.random_wet(33, 17, seed=9, dry_fraction=0.05)
+    runs = []
+    for s_ in (sc, inputs.mirror_x(sc), inputs.transpose(sc)):
+        o = oracle.Oracle.from_scenario(s_)
+        o.set_split(True)
+        assert o.step(12) == 0
+        runs.append(o.state())
+    (h, hu, hv), (hM, huM, hvM), (hT, huT, hvT) = runs
+    assert np.array_equal(hM, h[:, ::-1]) and np.array_equal(huM, -hu[:, ::-1])
+    assert np.array_equal(hT, h.T) and np.array_equal(huT, hv.T) and np.array_equal(hvT, hu.T)
+    o = oracle.Oracle.from_scenario(inputs.dam_break(nx=40, ny=3, x0=10.0))
+    o.set_split(True)
+    m0 = o.scalars()["mass"]
+    o.step(800)
+    assert abs(o.scalars()["mass"] - m0) <= 1e-13 * m0
