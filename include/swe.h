@@ -92,7 +92,10 @@ typedef struct swe_stats {
 /* ---- single scenario ---------------------------------------------------- */
 typedef struct swe_ctx swe_ctx;
 
-/* Create a scenario on the current HIP device.  b is the bed elevation [m],
+/* Create a scenario on the current HIP device: the inputs of the paper's
+ * problem statement (Methods: bathymetry b, Manning n, the initial state
+ * (h, hu, hv), the resolution; Sections 2.1-2.4 for the boundary kinds).
+ * b is the bed elevation [m] relative to the datum (the still-water level),
  * manning_n the Manning coefficient per cell, (h0, hu0, hv0) the initial
  * state; all [ny][nx] float32, host or device.  hip_stream is a hipStream_t
  * (NULL: the library creates its own); every later call of this context is
@@ -105,14 +108,18 @@ int swe_create(const swe_params *p, const float *b, const float *manning_n,
                const float *h0, const float *hu0, const float *hv0,
                void *hip_stream, swe_ctx **out);
 
-/* Enqueue nsteps RK3 steps (three stage launches each, dt computed on the
- * device).  Asynchronous; never blocks; a non-finite state surfaces at the
- * next swe_read.  nsteps < 0 is SWE_EINVAL; 0 is a no-op. */
+/* Enqueue nsteps RK3 steps (Methods, Eqs. (7)-(8): three stage launches
+ * each, every stage the WENO5 / Lax-Friedrichs operator with the bed and
+ * Manning sources; dt from the CFL condition, computed on the device).
+ * Asynchronous; never blocks; a non-finite state surfaces at the next
+ * swe_read.  nsteps < 0 is SWE_EINVAL; 0 is a no-op. */
 int swe_step(swe_ctx *ctx, int32_t nsteps);
 
 /* Wait for the context's stream, then copy the state (any of h, hu, hv may
- * be NULL) and the diagnostics (stats may be NULL).  Returns SWE_ENONFINITE
- * once a wave speed became non-finite (the copies are still made). */
+ * be NULL) and the diagnostics (stats may be NULL): the solution fields the
+ * paper's runs write out (Section 3), with the time, the mass (Section 2,
+ * conservation) and the runup (Section 2.4).  Returns SWE_ENONFINITE once a
+ * wave speed became non-finite (the copies are still made). */
 int swe_read(swe_ctx *ctx, float *h, float *hu, float *hv, swe_stats *stats);
 
 /* Release the context's device memory.  NULL-safe. */
@@ -129,8 +136,8 @@ void swe_destroy(swe_ctx *ctx);
  * cell and stage and about 19% more time per step.  0 (default): off.  Can
  * be switched at any time (the residual then starts at zero; the captured
  * graph is dropped).  Returns SWE_EINVAL for other values, SWE_ENOMEM when
- * the planes cannot be allocated (the option is then off).  Contexts only:
- * batches and servers run without it. */
+ * the planes cannot be allocated (the option is then off).  Batches take it
+ * through swe_batch_set_option and servers through swe_server_set_option. */
 #define SWE_OPT_COMPENSATED 3
 /* 1: point-implicit Manning friction (Methods: the paper keeps friction
  * explicit and names an implicit treatment as the alternative it declines).
@@ -144,6 +151,17 @@ void swe_destroy(swe_ctx *ctx);
  * SWE_EINVAL.  Batches and servers take it through swe_batch_set_option and
  * swe_server_set_option. */
 #define SWE_OPT_FRICTION_IMPLICIT 4
+/* 1: local Lax-Friedrichs splitting (Methods, Lax-Friedrichs paragraph: the
+ * paper splits with the global maximum speed of each stage).  Each face
+ * takes the largest normal speed |u_n| + sqrt(g h+) over the six cells its
+ * two reconstructions read and splits those cells with it; the face flux
+ * stays single-valued (conservative) and still water stays at rest.  Less
+ * viscosity where the flow is slow (wet/dry fronts); the time step stays
+ * global.  Each face then reconstructs its own split values (no sharing
+ * between neighbouring faces), about twice the arithmetic.  0 (default):
+ * the global speed.  Can be switched at any time (the captured graph is
+ * dropped); other values are SWE_EINVAL.  Contexts only. */
+#define SWE_OPT_LOCAL_SPLIT 5
 int swe_set_option(swe_ctx *ctx, int32_t key, int64_t value);
 
 /* Device addresses of the context's live state (depth h, hu, hv of u^n) and
@@ -269,13 +287,19 @@ int swe_batch_read(swe_batch *bt, int32_t index, float *h, float *hu, float *hv,
 #define SWE_BATCH_PERSISTENT 0 /* one persistent kernel, tile tickets, per-scenario barriers */
 #define SWE_BATCH_ROUNDS 1     /* one launch per stage covering every active scenario */
 int swe_batch_set_mode(swe_batch *bt, int32_t mode, int32_t use_graph);
-/* Tile variant used by the batch's launches (-1: automatic, from the
- * scenario with most cells).  All variants give bitwise identical states. */
+/* Tile variant used by the batch's launches (-1: automatic: the 128 x 16
+ * tile once the batch's tiles fill the GPU, 256 such tiles or more, else
+ * the choice for the scenario with most cells).  All variants give bitwise
+ * identical states. */
 int swe_batch_set_tile(swe_batch *bt, int32_t tile);
-/* Batch option: only SWE_OPT_FRICTION_IMPLICIT (0 or 1; Methods, the
- * friction variant described at that key), for every scenario of the batch
- * from the next swe_batch_run on.  A scenario then advances bitwise as a
- * context with the same option.  Other keys or values are SWE_EINVAL. */
+/* Batch options, 0 or 1, for every scenario of the batch from the next
+ * swe_batch_run on: SWE_OPT_FRICTION_IMPLICIT (Methods, the friction variant
+ * described at that key) and SWE_OPT_COMPENSATED (residual planes, 12 bytes
+ * per cell, for every scenario present and added later; switching it on
+ * starts the residuals at zero, off releases them).  A scenario then
+ * advances bitwise as a context with the same options.  Other keys or values
+ * are SWE_EINVAL; SWE_ENOMEM if residual planes cannot be allocated (the
+ * option is then off for every scenario). */
 int swe_batch_set_option(swe_batch *bt, int32_t key, int64_t value);
 /* Maximum-depth map of scenario `index`, as swe_track_max_depth for a
  * single scenario: with enable != 0 keep per cell the maximum of h over its
@@ -356,9 +380,10 @@ int swe_poll_ex(swe_server *sv, uint64_t ticket, swe_result *r, float *h, float 
 /* Launch mode of the server's segments (SWE_BATCH_ROUNDS, the default, or
  * SWE_BATCH_PERSISTENT); takes effect at the next segment. */
 int swe_server_set_mode(swe_server *sv, int32_t mode);
-/* Server option: only SWE_OPT_FRICTION_IMPLICIT (0 or 1), for every request;
- * settable before the first submit only (SWE_EBUSY after it), so that all
- * requests share one friction treatment.  Other keys or values are
+/* Server options, 0 or 1, for every request: SWE_OPT_FRICTION_IMPLICIT and
+ * SWE_OPT_COMPENSATED (each request's footprint then includes its three
+ * residual planes); settable before the first submit only (SWE_EBUSY after
+ * it), so that all requests share one treatment.  Other keys or values are
  * SWE_EINVAL. */
 int swe_server_set_option(swe_server *sv, int32_t key, int64_t value);
 

@@ -59,10 +59,11 @@ SegmentLauncher::~SegmentLauncher()
 }
 
 int SegmentLauncher::run(const std::vector<Geo> &geos, const std::vector<int> &ksteps, int vi, int mode,
-                         bool use_graph, hipStream_t stream, bool implicit)
+                         bool use_graph, hipStream_t stream, bool implicit, bool compensated)
 {
     const Variant &v = variant(vi);
-    const BatchKernels &K = implicit ? g_bk_imp[vi] : g_bk[vi];
+    const BatchKernels &K = compensated ? (implicit ? g_bk_cmp_imp[vi] : g_bk_cmp[vi])
+                                        : (implicit ? g_bk_imp[vi] : g_bk[vi]);
     const int n = (int)geos.size();
     std::vector<int> nxs(n), nys(n);
     for (int i = 0; i < n; ++i) {
@@ -179,6 +180,7 @@ struct BatchScen {
     int total = 0;  // requested steps
     int done = 0;   // steps enqueued so far
     float *hmax = nullptr;  // maximum-depth plane, when tracked
+    float *resid = nullptr; // residual planes of the compensated level, when on
 };
 
 struct swe_batch {
@@ -188,23 +190,32 @@ struct swe_batch {
     int mode = SWE_BATCH_ROUNDS;
     bool use_graph = true;
     int tile = -1;
-    bool implicit = false;  // point-implicit friction
+    bool implicit = false;     // point-implicit friction
+    bool compensated = false;  // compensated level (residual planes per scenario)
     SegmentLauncher seg;
 };
+
+// Gives scenario s residual planes (zeroed) or takes them away.
+static int batch_residuals(swe_batch *bt, BatchScen &s, bool on)
+{
+    if (s.resid) {
+        SWE_HIP_TRY(hipStreamSynchronize(bt->stream));
+        dev_free(s.resid);
+        s.resid = nullptr;
+        (void)attach_residuals(s.d.geo, nullptr, bt->stream);
+    }
+    if (!on) return SWE_OK;
+    const int arc = dev_alloc((void **)&s.resid, residual_bytes(s.p.nx, s.p.ny));
+    if (arc) return arc;
+    return attach_residuals(s.d.geo, s.resid, bt->stream);
+}
 
 static int batch_variant(const swe_batch *bt)
 {
     if (bt->tile >= 0) return bt->tile;
-    // the variant preferred for the scenario carrying most cells
-    size_t best = 0;
-    int nx = 0, ny = 0;
-    for (const auto &s : bt->sc)
-        if ((size_t)s.p.nx * s.p.ny > best) {
-            best = (size_t)s.p.nx * s.p.ny;
-            nx = s.p.nx;
-            ny = s.p.ny;
-        }
-    return default_variant(nx, ny);
+    std::vector<std::pair<int, int>> sizes;
+    for (const auto &s : bt->sc) sizes.emplace_back(s.p.nx, s.p.ny);
+    return batch_variant_for(sizes);
 }
 
 extern "C" {
@@ -241,6 +252,10 @@ int swe_batch_add(swe_batch *bt, const swe_params *p, const float *b, const floa
     SWE_HIP_TRY(hipStreamSynchronize(bt->stream));
     rc = scenario_upload(*p, f, bt->stream, s.d);
     if (rc) return rc;
+    if (bt->compensated && (rc = batch_residuals(bt, s, true))) {
+        scenario_free(s.d);
+        return rc;
+    }
     bt->sc.push_back(s);
     if (index) *index = (int32_t)bt->sc.size() - 1;
     return SWE_OK;
@@ -263,8 +278,21 @@ int swe_batch_set_tile(swe_batch *bt, int32_t tile)
 
 int swe_batch_set_option(swe_batch *bt, int32_t key, int64_t value)
 {
-    if (!bt || key != SWE_OPT_FRICTION_IMPLICIT || (value != 0 && value != 1)) return SWE_EINVAL;
-    bt->implicit = value != 0;
+    if (!bt || (value != 0 && value != 1)) return SWE_EINVAL;
+    if (key == SWE_OPT_FRICTION_IMPLICIT) {
+        bt->implicit = value != 0;
+        return SWE_OK;
+    }
+    if (key != SWE_OPT_COMPENSATED) return SWE_EINVAL;
+    for (auto &s : bt->sc) {
+        const int rc = batch_residuals(bt, s, value != 0);
+        if (rc) {
+            for (auto &q : bt->sc) (void)batch_residuals(bt, q, false);
+            bt->compensated = false;
+            return rc;
+        }
+    }
+    bt->compensated = value != 0;
     return SWE_OK;
 }
 
@@ -279,7 +307,8 @@ int swe_batch_run(swe_batch *bt, int32_t max_steps)
         geos.push_back(s.d.geo);
         ks.push_back(k);
     }
-    const int rc = bt->seg.run(geos, ks, batch_variant(bt), bt->mode, bt->use_graph, bt->stream, bt->implicit);
+    const int rc = bt->seg.run(geos, ks, batch_variant(bt), bt->mode, bt->use_graph, bt->stream, bt->implicit,
+                               bt->compensated);
     if (rc) return rc;
     for (size_t i = 0; i < bt->sc.size(); ++i) bt->sc[i].done += ks[i];
     return SWE_OK;
@@ -334,6 +363,7 @@ void swe_batch_destroy(swe_batch *bt)
     if (bt->stream) (void)hipStreamSynchronize(bt->stream);
     for (auto &s : bt->sc) {
         dev_free(s.hmax);
+        dev_free(s.resid);
         scenario_free(s.d);
     }
     if (bt->own_stream && bt->stream) (void)hipStreamDestroy(bt->stream);

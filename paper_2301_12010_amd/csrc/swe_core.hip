@@ -221,12 +221,11 @@ int launch_stage(const Variant &v, int stage, const Geo &g, hipStream_t stream)
 {
     const int ntx = (g.nx + v.tx - 1) / v.tx, nty = (g.ny + v.ty - 1) / v.ty;
     const int nb = ntx * nty;
-    const int mode = (g.Rl[0] ? 1 : 0) + (g.fric_implicit ? 2 : 0);
+    const int mode = (g.Rl[0] ? 1 : 0) + (g.fric_implicit ? 2 : 0) + (g.local_split ? 4 : 0);
     const int vi = (int)(&v - g_variants);
-    void (*k)(Geo, int, int) = v.stage[stage - 1];
-    if (mode == 1) k = g_stage_mode1[vi].k[stage - 1];
-    if (mode == 2) k = g_stage_mode2[vi].k[stage - 1];
-    if (mode == 3) k = g_stage_mode3[vi].k[stage - 1];
+    static const StageSet *const sets[8] = {nullptr, g_stage_mode1, g_stage_mode2, g_stage_mode3,
+                                            g_stage_mode4, g_stage_mode5, g_stage_mode6, g_stage_mode7};
+    void (*k)(Geo, int, int) = mode ? sets[mode][vi].k[stage - 1] : v.stage[stage - 1];
     hipLaunchKernelGGL(k, dim3(nb), dim3(v.nt), 0, stream, g, ntx, nb);
     return hipGetLastError() == hipSuccess ? SWE_OK : SWE_EDEVICE;
 }
@@ -360,6 +359,7 @@ void geo_layout(void *mem, const swe_params &p, Geo &g)
     g.eps16 = (float)(16.0 * p.weno_eps);
     g.kappa_cap = (float)p.kappa_cap;
     g.fric_implicit = 0;
+    g.local_split = 0;
     g.cfl = (float)p.cfl;
     g.dt_fixed = (float)p.dt_fixed;
     float *planes[11];
@@ -511,6 +511,15 @@ int scenario_upload(const swe_params &p, const HostFields &f, hipStream_t stream
         d.base = nullptr;
     }
     return rc;
+}
+
+int attach_residuals(Geo &g, float *mem, hipStream_t stream)
+{
+    const size_t plane = (size_t)g.pitch * g.ny;
+    for (int k = 0; k < 3; ++k) g.Rl[k] = mem ? mem + k * plane : nullptr;
+    // the stored FP32 level is exact as it stands: residuals start at 0
+    if (mem) SWE_HIP_TRY(hipMemsetAsync(mem, 0, residual_bytes(g.nx, g.ny), stream));
+    return SWE_OK;
 }
 
 void scenario_free(DevScenario &d)
@@ -976,6 +985,12 @@ int swe_set_option(swe_ctx *c, int32_t key, int64_t value)
         c->d.geo.fric_implicit = (int)value;
         return SWE_OK;
     }
+    if (key == SWE_OPT_LOCAL_SPLIT) {
+        if (value != 0 && value != 1) return SWE_EINVAL;
+        drop_graph(c);  // captured steps launch the kernels of the mode
+        c->d.geo.local_split = (int)value;
+        return SWE_OK;
+    }
     if (key == SWE_OPT_COMPENSATED) {
         if (value != 0 && value != 1) return SWE_EINVAL;
         drop_graph(c);  // captured steps carry the planes' addresses
@@ -987,13 +1002,9 @@ int swe_set_option(swe_ctx *c, int32_t key, int64_t value)
             for (int k = 0; k < 3; ++k) g.Rl[k] = nullptr;
         }
         if (!value) return SWE_OK;
-        const size_t plane = (size_t)g.pitch * g.ny;
-        const int arc = dev_alloc((void **)&c->d_resid, 3 * plane * sizeof(float));
+        const int arc = dev_alloc((void **)&c->d_resid, residual_bytes(g.nx, g.ny));
         if (arc) return arc;
-        // the stored FP32 level is exact as it stands: residuals start at 0
-        SWE_HIP_TRY(hipMemsetAsync(c->d_resid, 0, 3 * plane * sizeof(float), c->stream));
-        for (int k = 0; k < 3; ++k) g.Rl[k] = c->d_resid + k * plane;
-        return SWE_OK;
+        return attach_residuals(g, c->d_resid, c->stream);
     }
     return SWE_EINVAL;
 }

@@ -7,6 +7,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <utility>
 #include <vector>
 
 #include "../../include/swe.h"
@@ -96,21 +97,26 @@ struct Variant {
     X(16, 16, 2, 2)      \
     X(16, 16, 1, 2)
 // Stage kernels of every tile variant (in SWE_TILE_LIST order) in the
-// optional modes of a context: 1 the compensated level, 2 point-implicit
-// friction, 3 both.  One translation unit per mode (swe_mode<N>.hip), so the
-// sets compile in parallel.
+// optional modes of a context, mode = CMP + 2 IMP + 4 LLF: 1 the compensated
+// level, 2 point-implicit friction, 4 local Lax-Friedrichs splitting, and
+// their sums.  One translation unit per mode (swe_mode<N>.hip), so the sets
+// compile in parallel.
 struct StageSet {
     void (*k[3])(Geo, int, int);
 };
-#define SWE_STAGE_SET(TX, TY, R, W, CMP, IMP)                                                       \
-    {{k_stage<TileCfg<TX, TY, R>, 1, W, CMP, IMP>, k_stage<TileCfg<TX, TY, R>, 2, W, CMP, IMP>,      \
-      k_stage<TileCfg<TX, TY, R>, 3, W, CMP, IMP>}},
-extern const StageSet g_stage_mode1[], g_stage_mode2[], g_stage_mode3[];
+#define SWE_STAGE_SET_L(TX, TY, R, W, CMP, IMP, LLF)                                                 \
+    {{k_stage<TileCfg<TX, TY, R>, 1, W, CMP, IMP, LLF>, k_stage<TileCfg<TX, TY, R>, 2, W, CMP, IMP, LLF>, \
+      k_stage<TileCfg<TX, TY, R>, 3, W, CMP, IMP, LLF>}},
+#define SWE_STAGE_SET(TX, TY, R, W, CMP, IMP) SWE_STAGE_SET_L(TX, TY, R, W, CMP, IMP, false)
+extern const StageSet g_stage_mode1[], g_stage_mode2[], g_stage_mode3[], g_stage_mode4[], g_stage_mode5[],
+    g_stage_mode6[], g_stage_mode7[];
 // depth h = s - min(b, 0) of a stored-level plane into out (same pitch)
 int launch_depth(const Geo &g, const float *lev, float *out, hipStream_t stream);
 int variant_count();
 const Variant &variant(int i);
 int default_variant(int nx, int ny);
+// variant of one launch over scenarios of these (nx, ny) sizes
+int batch_variant_for(const std::vector<std::pair<int, int>> &sizes);
 int launch_stage(const Variant &v, int stage, const Geo &g, hipStream_t stream);
 
 double now_seconds();
@@ -128,9 +134,16 @@ struct SegmentLauncher {
     int cus = 0;
     int group = 0;  // tickets taken per atomic in persistent mode (0: automatic)
     ~SegmentLauncher();
-    // implicit: the point-implicit friction kernels
+    // implicit: the point-implicit friction kernels; compensated: the
+    // compensated-level kernels (every geo then has residual planes)
     int run(const std::vector<Geo> &geos, const std::vector<int> &ksteps, int vi, int mode, bool use_graph,
-            hipStream_t stream, bool implicit = false);
+            hipStream_t stream, bool implicit = false, bool compensated = false);
 };
+
+// Residual planes of the compensated level for one scenario: `mem` holds
+// three planes of the scenario's pitch x ny floats; they are zeroed on
+// `stream` and attached to g (mem == nullptr detaches them).
+int attach_residuals(Geo &g, float *mem, hipStream_t stream);
+inline size_t residual_bytes(int nx, int ny) { return (size_t)plane_pitch(nx) * ny * sizeof(float) * 3; }
 
 }  // namespace swe

@@ -111,11 +111,16 @@ struct Request {
 };
 
 // Device bytes of a request: its scenario, plus one plane for the
-// maximum-depth map when it keeps one.
-static size_t request_bytes(const swe_params &p, bool track_max)
+// maximum-depth map when it keeps one, plus three residual planes when the
+// server runs the compensated level.
+static size_t map_bytes(const swe_params &p)
 {
-    const size_t plane = ((size_t)plane_pitch(p.nx) * p.ny * sizeof(float) + 255) / 256 * 256;
-    return scenario_bytes(p.nx, p.ny) + (track_max ? plane : 0);
+    return ((size_t)plane_pitch(p.nx) * p.ny * sizeof(float) + 255) / 256 * 256;
+}
+static size_t request_bytes(const swe_params &p, bool track_max, bool compensated)
+{
+    return scenario_bytes(p.nx, p.ny) + (track_max ? map_bytes(p) : 0) +
+           (compensated ? residual_bytes(p.nx, p.ny) : 0);
 }
 
 }  // namespace swe
@@ -127,7 +132,8 @@ struct swe_server {
     int max_slots = 64;
     int segment_steps = 100;
     int mode = SWE_BATCH_ROUNDS;
-    bool implicit = false;  // point-implicit friction (set before the first submit)
+    bool implicit = false;     // point-implicit friction (set before the first submit)
+    std::atomic<bool> compensated{false};  // compensated level (set before the first submit)
     size_t max_queue = 1 << 16;
     Arena arena;
     hipStream_t compute = nullptr, copy = nullptr;
@@ -169,7 +175,7 @@ int swe_server::admit_locked(std::vector<Request *> &admitted)
             finish(r, SWE_CANCELLED, SWE_OK);
             continue;
         }
-        void *mem = arena.alloc(request_bytes(r->p, r->track_max));
+        void *mem = arena.alloc(request_bytes(r->p, r->track_max, compensated));
         if (!mem) break;  // FIFO: wait for memory to free up
         queue.pop_front();
         r->d.base = mem;
@@ -209,9 +215,8 @@ void swe_server::loop()
         }
         int rc = SWE_OK;
         if (!in_seg.empty()) {
-            int big = 0;
-            for (size_t i = 1; i < geos.size(); ++i)
-                if ((size_t)geos[i].nx * geos[i].ny > (size_t)geos[big].nx * geos[big].ny) big = (int)i;
+            std::vector<std::pair<int, int>> sizes;
+            for (const Geo &g : geos) sizes.emplace_back(g.nx, g.ny);
             int launch_mode;
             bool launch_implicit;
             {
@@ -219,8 +224,8 @@ void swe_server::loop()
                 launch_mode = mode;
                 launch_implicit = implicit;
             }
-            rc = seg.run(geos, ks, default_variant(geos[big].nx, geos[big].ny), launch_mode, false, compute,
-                         launch_implicit);
+            rc = seg.run(geos, ks, batch_variant_for(sizes), launch_mode, false, compute, launch_implicit,
+                         compensated);
             std::lock_guard<std::mutex> lk(mu);
             ++segments;
             if (rc) fatal = rc;
@@ -236,10 +241,16 @@ void swe_server::loop()
                                                           scenario_bytes(r->p.nx, r->p.ny));
                 urc = launch_depth(r->d.geo, r->d.geo.U[0], r->d.geo.hmax, copy);
             }
+            if (!urc && compensated) {
+                // the residual planes come last
+                char *rp = static_cast<char *>(r->d.base) + scenario_bytes(r->p.nx, r->p.ny) +
+                           (r->track_max ? map_bytes(r->p) : 0);
+                urc = attach_residuals(r->d.geo, reinterpret_cast<float *>(rp), copy);
+            }
             std::lock_guard<std::mutex> lk(mu);
             r->f = HostFields();
             if (urc) {
-                arena.release(r->d.base, request_bytes(r->p, r->track_max));
+                arena.release(r->d.base, request_bytes(r->p, r->track_max, compensated));
                 r->d.base = nullptr;
                 finish(r, SWE_FAILED, urc);
             } else {
@@ -267,7 +278,7 @@ void swe_server::loop()
                 if (!rrc) rrc = src;
             }
             std::lock_guard<std::mutex> lk(mu);
-            arena.release(r->d.base, request_bytes(r->p, r->track_max));
+            arena.release(r->d.base, request_bytes(r->p, r->track_max, compensated));
             r->d.base = nullptr;
             if (r->cancel) finish(r, SWE_CANCELLED, SWE_OK);
             else if (rrc == SWE_OK) finish(r, SWE_DONE, SWE_OK);
@@ -295,7 +306,7 @@ void swe_server::loop()
                 }
             if (out) {
                 if (r->error != SWE_OK && !r->cancel) {
-                    arena.release(r->d.base, request_bytes(r->p, r->track_max));
+                    arena.release(r->d.base, request_bytes(r->p, r->track_max, compensated));
                     r->d.base = nullptr;
                     finish(r, SWE_FAILED, r->error);
                 } else {
@@ -357,7 +368,7 @@ int swe_submit_ex(swe_server *sv, const swe_params *p, const float *b, const flo
     int rc = load_fields(p, b, n, h0, hu0, hv0, r->f);
     if (rc) return rc;
     r->track_max = (flags & SWE_SUBMIT_MAX_DEPTH) != 0;
-    if (request_bytes(*p, r->track_max) > sv->arena.capacity()) return SWE_ENOMEM;
+    if (request_bytes(*p, r->track_max, sv->compensated) > sv->arena.capacity()) return SWE_ENOMEM;
     r->p = *p;
     r->nsteps = nsteps;
     r->t_submit = now_seconds();
@@ -423,10 +434,12 @@ int swe_server_set_mode(swe_server *sv, int32_t mode)
 
 int swe_server_set_option(swe_server *sv, int32_t key, int64_t value)
 {
-    if (!sv || key != SWE_OPT_FRICTION_IMPLICIT || (value != 0 && value != 1)) return SWE_EINVAL;
+    if (!sv || (key != SWE_OPT_FRICTION_IMPLICIT && key != SWE_OPT_COMPENSATED) || (value != 0 && value != 1))
+        return SWE_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->submitted > 0) return SWE_EBUSY;  // one treatment for every request
-    sv->implicit = value != 0;
+    if (key == SWE_OPT_FRICTION_IMPLICIT) sv->implicit = value != 0;
+    else sv->compensated = value != 0;
     return SWE_OK;
 }
 

@@ -63,6 +63,7 @@ struct Geo {
     float g, half_g, h_dry, eps16;  // eps16 = 16 * weno_eps (the kernels' indicator scale)
     float kappa_cap, cfl, dt_fixed;
     int fric_implicit;       // 1: point-implicit friction (the host launches the IMP kernels)
+    int local_split;         // 1: local Lax-Friedrichs splitting (the host launches the LLF kernels)
     const float *b, *gn2;    // bed and g n^2 planes
     // u^n, u^(1), u^(2): planes of (s, hu, hv) where s = h + min(b, 0) is the
     // stored level: the surface elevation h + b where the bed lies below the
@@ -337,6 +338,147 @@ __device__ __forceinline__ void sweep(const float *__restrict__ Ls, const float 
     }
 }
 
+// WENO5-JS of one five-value stencil v (doubled split values, read in the
+// upwind direction; the face lies between v[2] and v[3]): the unnormalised
+// weights a0..a2 (indicators carried 16-fold as in sweep()) and the
+// numerator sum a_k q_k; the reconstruction is num / (a0 + a1 + a2).
+__device__ __forceinline__ void weno5_face(const float v[5], const SweepK &K, float &num, float a[3])
+{
+    const float d0 = fmaf(-2.f, v[1], v[0] + v[2]);
+    const float d1 = fmaf(-2.f, v[2], v[1] + v[3]);
+    const float d2 = fmaf(-2.f, v[3], v[2] + v[4]);
+    const float s0 = fmaf(3.f, v[2], fmaf(-4.f, v[1], v[0]));
+    const float s1 = v[1] - v[3];
+    const float s2 = fmaf(3.f, v[2], fmaf(-4.f, v[3], v[4]));
+    a[0] = wt(fmaf(s0, s0, ((13.f / 3.f) * d0) * d0), KD0, K.e0);
+    a[1] = wt(fmaf(s1, s1, ((13.f / 3.f) * d1) * d1), KD1, K.e1);
+    a[2] = wt(fmaf(s2, s2, ((13.f / 3.f) * d2) * d2), KD2, K.e2);
+    // candidate polynomials at the face
+    const float q0 = fmaf(11.f, v[2], fmaf(-7.f, v[1], 2.f * v[0])) * (1.f / 6.f);
+    const float q1 = fmaf(2.f, v[3], fmaf(5.f, v[2], -v[1])) * (1.f / 6.f);
+    const float q2 = fmaf(-1.f, v[4], fmaf(5.f, v[3], 2.f * v[2])) * (1.f / 6.f);
+    num = fmaf(a[2], q2, fmaf(a[1], q1, a[0] * q0));
+}
+
+// The same candidates of a stencil of b, combined with given weights.
+__device__ __forceinline__ float weno5_with(const float v[5], const float a[3])
+{
+    const float q0 = fmaf(11.f, v[2], fmaf(-7.f, v[1], 2.f * v[0])) * (1.f / 6.f);
+    const float q1 = fmaf(2.f, v[3], fmaf(5.f, v[2], -v[1])) * (1.f / 6.f);
+    const float q2 = fmaf(-1.f, v[4], fmaf(5.f, v[3], 2.f * v[2])) * (1.f / 6.f);
+    return fmaf(a[2], q2, fmaf(a[1], q1, a[0] * q0));
+}
+
+// One sweep with local Lax-Friedrichs splitting (an option; the paper splits
+// with the global speed of the stage, Methods, Lax-Friedrichs paragraph).
+// Face-based: face f of the segment (between cells f-1 and f, f = 0..R)
+// takes the largest normal speed |u_n| + sqrt(g h+) over the six cells its
+// two reconstructions read (f-3..f+2), splits those cells with it and runs
+// both reconstructions of every component itself: with a speed per face the
+// split values differ from face to face, so the per-centre sharing of
+// sweep() does not apply.  Same interface and emitted quantities as sweep().
+template <int R, int DIR, class Emit>
+__device__ __forceinline__ void sweep_llf(const float *__restrict__ Ls, const float *__restrict__ Lhu,
+                                          const float *__restrict__ Lhv, const float *__restrict__ Lb,
+                                          int li0, int st, const SweepK &K, Emit &&emit)
+{
+    constexpr int MB = DIR == 0 ? 1 : 2;
+    float wf[6][3], wu[6][3], wb[6], ws[6];  // cells f-3..f+2: flux, split vector, bed, speed
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        wf[q][0] = wf[q][1] = wf[q][2] = wu[q][0] = wu[q][1] = wu[q][2] = 0.f;
+        wb[q] = ws[q] = 0.f;
+    }
+    float eta[R];
+    float fprev[3] = {0.f, 0.f, 0.f}, bprev = 0.f;
+#pragma unroll
+    for (int w = -HALO; w < R + HALO; ++w) {
+        const int li = li0 + (w + HALO) * st;
+        const float sv = Ls[li], hu = Lhu[li], hv = Lhv[li], b = Lb[li];
+        const float lo = fminf(b, 0.f);
+        const float h = sv - lo;
+        const float inv = h > K.h_dry ? frcp(h) : 0.f;
+        const float pres = K.half_g * (h - lo) * sv;
+        float F0, F1, F2, un;
+        if (DIR == 0) {
+            un = hu * inv;
+            F0 = hu;
+            F1 = fmaf(hu, un, pres);
+            F2 = hu * (hv * inv);
+        } else {
+            un = hv * inv;
+            F0 = hv;
+            F1 = hv * (hu * inv);
+            F2 = fmaf(hv, un, pres);
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                wf[q][m] = wf[q + 1][m];
+                wu[q][m] = wu[q + 1][m];
+            }
+            wb[q] = wb[q + 1];
+            ws[q] = ws[q + 1];
+        }
+        wf[5][0] = F0;
+        wf[5][1] = F1;
+        wf[5][2] = F2;
+        wu[5][0] = sv;
+        wu[5][1] = hu;
+        wu[5][2] = hv;
+        wb[5] = b;
+        ws[5] = fabsf(un) + sqrtf(K.g * fmaxf(h, 0.f));
+        if (w >= 0 && w < R) eta[w >= 0 && w < R ? w : 0] = sv;
+        if (w < 2) continue;
+        const int f = w - 2;  // face between cells f-1 and f: its window is complete
+        const float a = fmaxf(fmaxf(fmaxf(ws[0], ws[1]), fmaxf(ws[2], ws[3])), fmaxf(ws[4], ws[5]));
+        float Fh[3], ap_b[3], am_b[3], rp_b = 0.f, rm_b = 0.f;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            float vp[5], vm[5], ap[3], am[3], np_, nm_;
+#pragma unroll
+            for (int s = 0; s < 5; ++s) {
+                vp[s] = fmaf(a, wu[s][m], wf[s][m]);            // cells f-3 .. f+1
+                vm[s] = fmaf(-a, wu[5 - s][m], wf[5 - s][m]);   // cells f+2 .. f-2
+            }
+            weno5_face(vp, K, np_, ap);
+            weno5_face(vm, K, nm_, am);
+            const float rp = frcp(ap[0] + ap[1] + ap[2]);
+            const float rm = frcp(am[0] + am[1] + am[2]);
+            Fh[m] = fmaf(np_, rp, nm_ * rm);
+            if (m == MB) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    ap_b[k] = ap[k];
+                    am_b[k] = am[k];
+                }
+                rp_b = rp;
+                rm_b = rm;
+            }
+        }
+        float bp[5], bm[5];
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+            bp[s] = wb[s];
+            bm[s] = wb[5 - s];
+        }
+        // twice the face value of b (mean of the two reconstructions)
+        const float bh = fmaf(weno5_with(bp, ap_b), rp_b, weno5_with(bm, am_b) * rm_b);
+        if (f >= 1) {
+            const int k = f - 1;
+            float r3[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) r3[m] = (fprev[m] - Fh[m]) * K.hinv_ds;
+            r3[MB] = fmaf(eta[k], (bh - bprev) * K.ghinv_ds, r3[MB]);
+            emit(k, r3[0], r3[1], r3[2]);
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) fprev[m] = Fh[m];
+        bprev = bh;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // wave64 reductions
 // ---------------------------------------------------------------------------
@@ -517,7 +659,7 @@ __device__ __forceinline__ void tile_store(const Geo &G, int tx, int ty, const T
 // backward in time with the rate kappa of its input, uncapped:
 // q_out = [a_n q^n + a_w (q + dt L')] / (1 + a_w dt kappa), L' without
 // friction, a_w = 1, 1/4, 2/3 (an option; the paper's friction is explicit).
-template <class C, bool PF, bool CMP, bool IMP>
+template <class C, bool PF, bool CMP, bool IMP, bool LLF = false>
 __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &sc, int tx, int ty, float *lds,
                                              StagePartials &acc)
 {
@@ -545,12 +687,15 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
         K.hinv_ds = 0.5f * G.inv_dx;
         K.ghinv_ds = -G.g * K.hinv_ds;
         float *xo = Xr + row * C::XR + seg * R;
-        sweep<R, 0>(Ls, Lhu, Lhv, Lb, (row + HALO) * C::SX + seg * R, 1, K,
-                    [&](int k, float l0, float l1, float l2) {
-                        xo[k] = l0;
-                        xo[C::XPLANE + k] = l1;
-                        xo[2 * C::XPLANE + k] = l2;
-                    });
+        auto xput = [&](int k, float l0, float l1, float l2) {
+            xo[k] = l0;
+            xo[C::XPLANE + k] = l1;
+            xo[2 * C::XPLANE + k] = l2;
+        };
+        if constexpr (LLF)
+            sweep_llf<R, 0>(Ls, Lhu, Lhv, Lb, (row + HALO) * C::SX + seg * R, 1, K, xput);
+        else
+            sweep<R, 0>(Ls, Lhu, Lhv, Lb, (row + HALO) * C::SX + seg * R, 1, K, xput);
     }
     __syncthreads();
 
@@ -710,7 +855,10 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
             }
         }
     };
-    sweep<R, 1>(Ls, Lhu, Lhv, Lb, (seg * R) * C::SX + col + HALO, C::SX, K, cell);
+    if constexpr (LLF)
+        sweep_llf<R, 1>(Ls, Lhu, Lhv, Lb, (seg * R) * C::SX + col + HALO, C::SX, K, cell);
+    else
+        sweep<R, 1>(Ls, Lhu, Lhv, Lb, (seg * R) * C::SX + col + HALO, C::SX, K, cell);
 }
 
 // Block reduction of the partials and the stage's atomics.  `first` marks
@@ -783,7 +931,7 @@ __device__ __forceinline__ void stage_publish(const Geo &G, const StageScalars &
 
 // The whole stage on one tile (one block, one tile).
 // PF and IMP as for tile_compute; CMP: the compensated level (Geo::Rl set).
-template <class C, bool PF, bool CMP = false, bool IMP = false>
+template <class C, bool PF, bool CMP = false, bool IMP = false, bool LLF = false>
 __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *lds, const int STAGE)
 {
     const StageScalars sc = stage_scalars(G, STAGE);
@@ -798,7 +946,7 @@ __device__ __forceinline__ void stage_tile(const Geo &G, int tx, int ty, float *
     }
     __syncthreads();
     StagePartials acc;
-    tile_compute<C, PF, CMP, IMP>(G, sc, tx, ty, lds, acc);
+    tile_compute<C, PF, CMP, IMP, LLF>(G, sc, tx, ty, lds, acc);
     stage_publish<C>(G, sc, acc, tx == 0 && ty == 0, lds);
 }
 
@@ -812,13 +960,13 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
 }
 
 // The stage kernel: one tile per block.  CMP selects the compensated level,
-// IMP the point-implicit friction.
-template <class C, int S, int W, bool CMP = false, bool IMP = false>
+// IMP the point-implicit friction, LLF the local Lax-Friedrichs splitting.
+template <class C, int S, int W, bool CMP = false, bool IMP = false, bool LLF = false>
 __global__ __launch_bounds__(C::NT, W) void k_stage(Geo G, int ntx, int nblocks)
 {
     __shared__ float lds[C::LDS_FLOATS];
     const int id = xcd_remap(blockIdx.x, nblocks);
-    stage_tile<C, (W <= 2), CMP, IMP>(G, id % ntx, id / ntx, lds, S);
+    stage_tile<C, (W <= 2), CMP, IMP, LLF>(G, id % ntx, id / ntx, lds, S);
 }
 
 }  // namespace swe

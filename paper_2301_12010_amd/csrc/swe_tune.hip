@@ -53,6 +53,29 @@ int default_variant(int nx, int ny)
     return tiles >= 64 ? variant_by_shape(64, 16, 4) : variant_by_shape(32, 16, 2);
 }
 
+// Variant of a launch over several scenarios (a batch run or a server
+// segment).  Once their 128x16 tiles number 256 or more together, the GPU is
+// full whatever each grid's size, and the 128x16 tile with 8 cells per
+// thread (the fewest instructions per cell) is the fastest for the mix: the
+// size a grid alone would be tuned to only matters when the launch cannot
+// fill the GPU.  Otherwise the largest scenario's own choice.
+int batch_variant_for(const std::vector<std::pair<int, int>> &sizes)
+{
+    long long tiles = 0;
+    size_t big = 0;
+    int nx = 0, ny = 0;
+    for (const auto &s : sizes) {
+        tiles += (long long)((s.first + 127) / 128) * ((s.second + 15) / 16);
+        if ((size_t)s.first * s.second > big) {
+            big = (size_t)s.first * s.second;
+            nx = s.first;
+            ny = s.second;
+        }
+    }
+    if (tiles >= 256) return variant_by_shape(128, 16, 8);
+    return default_variant(nx, ny);
+}
+
 static std::string arch_name()
 {
     int dev = 0;

@@ -17,7 +17,7 @@ LIB_PATH = _PKG / "libswe.so"
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 BC_REFLECT, BC_FIXED = 0, 1
-OPT_GRAPH_STEPS, OPT_TILE, OPT_COMPENSATED, OPT_FRICTION_IMPLICIT = 1, 2, 3, 4
+OPT_GRAPH_STEPS, OPT_TILE, OPT_COMPENSATED, OPT_FRICTION_IMPLICIT, OPT_LOCAL_SPLIT = 1, 2, 3, 4, 5
 BATCH_PERSISTENT, BATCH_ROUNDS = 0, 1
 PENDING, DONE, FAILED, CANCELLED = 0, 1, 2, 3
 SUBMIT_MAX_DEPTH = 1

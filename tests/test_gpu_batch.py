@@ -162,3 +162,39 @@ def test_nwave_beach_with_hill_against_checker():
     assert_front_parity(g, o.state(), TOL_SHOCK, "nwave")
     assert_epilogue_parity(g[3], o.scalars(), sc, "nwave")
     bt.close()
+
+
+@pytest.mark.parametrize("mode,graph", [(swe.BATCH_ROUNDS, True), (swe.BATCH_PERSISTENT, False)])
+def test_compensated_batch_equals_compensated_contexts_and_keeps_mass(mode, graph):
+    # the compensated level in a batch (SWE_OPT_COMPENSATED): each member
+    # advances bitwise as a context with the option, and the mass balance of
+    # the shallow 256^2 beach scenario holds to 1e-12 of the mass per step
+    plan = inputs.uneven_plan()
+    small = next(i for i, (sz, _) in enumerate(plan) if sz == (256, 256))
+    mix = [(inputs.uneven_scenario(small, plan), 400), (inputs.random_wet(130, 70, seed=2, dry_fraction=0.05), 9),
+           (inputs.parabolic_bowl(nx=150, ny=9, dx=4.0), 31)]
+    bt = swe.Batch()
+    bt.set_mode(mode, graph)
+    bt.set_tile(1)
+    bt.add_scenario(*mix[0])
+    bt.set_option(swe.OPT_COMPENSATED, 1)  # present members get planes ...
+    for sc, n in mix[1:]:
+        bt.add_scenario(sc, n)             # ... and members added later too
+    m0 = bt.stats(0)["mass"]
+    bt.run()
+    for i, (sc, n) in enumerate(mix):
+        g = bt.read(i)
+        s = swe.Solver.from_scenario(sc)
+        s.set_option(swe.OPT_TILE, 1)
+        s.set_option(swe.OPT_COMPENSATED, 1)
+        s.step(n)
+        ref = s.read()
+        s.close()
+        for a, b in zip(g[:3], ref[:3]):
+            assert np.array_equal(a, b), sc.name
+        if i == 0:
+            drift = (g[3]["mass"] - m0 - g[3]["clamp_mass"]) / m0 / n
+            say("compensated batch mass drift per step", drift)
+            assert abs(drift) <= 1e-12
+    bt.set_option(swe.OPT_COMPENSATED, 0)
+    bt.close()

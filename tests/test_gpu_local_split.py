@@ -1,0 +1,137 @@
+"""GPU: local Lax-Friedrichs splitting (SWE_OPT_LOCAL_SPLIT) against the FP64
+checker's variant (reading R11), element by element on the same seeded
+inputs; still water stays at rest; every tile variant and the transposed
+problem give the same state bitwise; the 4096^2 coastline in the launch
+configuration the bench times for it."""
+import sys
+
+import numpy as np
+import pytest
+
+import analytic as A
+import oracle
+from parity import (TOL_SHOCK, TOL_SMOOTH, assert_epilogue_parity, assert_front_parity,
+                    field_errors, film_mass)
+from paper_2301_12010_amd import inputs, swe
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_run(sc, nsteps, tile=None, implicit=0, graph_steps=None):
+    say(f"case {sc.name} {sc.params.nx}x{sc.params.ny} steps={nsteps} local split, implicit={implicit} "
+        f"tile={tile}")
+    s = swe.Solver.from_scenario(sc)
+    s.set_option(swe.OPT_LOCAL_SPLIT, 1)
+    s.set_option(swe.OPT_FRICTION_IMPLICIT, implicit)
+    if tile is not None:
+        s.set_option(swe.OPT_TILE, tile)
+    if graph_steps is not None:
+        s.set_option(swe.OPT_GRAPH_STEPS, graph_steps)
+    s.step(nsteps)
+    h, hu, hv, st = s.read()
+    s.close()
+    assert st["status"] == swe.OK
+    return (h, hu, hv), st
+
+
+def checker_run(sc, nsteps, implicit=False):
+    o = oracle.Oracle.from_scenario(sc)
+    o.set_split(True)
+    o.set_friction(implicit)
+    assert o.step(nsteps) == 0
+    return o.state(), o.scalars()
+
+
+@pytest.mark.parametrize("nx,ny", [(7, 7), (33, 17), (130, 70)])
+def test_random_wet_matches_checker(nx, ny):
+    sc = inputs.random_wet(nx, ny, seed=500 + nx * 3 + ny)
+    for n in (1, 5):
+        g, st = gpu_run(sc, n)
+        r, rs = checker_run(sc, n)
+        e = field_errors(g, r)
+        say("errors", e)
+        assert max(e) <= TOL_SMOOTH, e
+        assert abs(st["t"] - rs["t"]) <= 1e-6 * rs["t"]
+
+
+def test_random_wet_dry_with_implicit_friction():
+    sc = inputs.random_wet(100, 37, seed=77, dry_fraction=0.1, manning=0.05)
+    g, st = gpu_run(sc, 5, implicit=1)
+    r, rs = checker_run(sc, 5, implicit=True)
+    e = field_errors(g, r)
+    say("errors", e)
+    assert max(e) <= TOL_SHOCK, e
+
+
+def test_dam_break_against_checker_and_stoker():
+    sc = inputs.dam_break()
+    g, st = gpu_run(sc, sc.nsteps)
+    r, rs = checker_run(sc, sc.nsteps)
+    e = field_errors(g, r)
+    say("dam break errors", e)
+    assert max(e) <= TOL_SHOCK, e
+    x = np.arange(128) + 0.5
+    assert A.rel_l2(g[0][10], A.dam_break_h(x, st["t"], 2.0, 1.0, 64.0)) < 2e-2
+    assert np.all(g[2] == 0.0)
+    assert_epilogue_parity(st, rs, sc, "dam break, local split")
+
+
+def test_parabolic_bowl_wet_dry():
+    # with the local speed the viscosity at the fronts is small, and a
+    # sub-threshold film creeps onto the dry flank by increments below the
+    # FP32 resolution of the neighbouring wet level: the checker grows it to
+    # 2e-4 m over 300 steps in one cell, the FP32 path does not (and clamps
+    # less instead).  Away from such films the results agree as usual.
+    sc = inputs.parabolic_bowl(nx=300, ny=8, dx=2.0)
+    g, st = gpu_run(sc, 300)
+    r, rs = checker_run(sc, 300)
+    assert_front_parity(g, r, TOL_SHOCK, "bowl, local split")
+    films = film_mass(g, r, sc)
+    assert films <= 1e-5 * rs["mass"]
+    assert_epilogue_parity(st, rs, sc, "bowl, local split", films=films)
+
+
+def test_still_water_stays_at_rest():
+    sc = inputs.still_coast()
+    g, st = gpu_run(sc, 200, graph_steps=50)
+    assert np.array_equal(g[0], sc.h) and not g[1].any() and not g[2].any()
+    assert st["runup"] == 0.0 and st["clamp_mass"] == 0.0
+    sc = inputs.lake_at_rest()
+    g, st = gpu_run(sc, 300)
+    eta0 = sc.h.astype(np.float64) + sc.b
+    c = np.sqrt(9.81 * g[0].max())
+    vel = max(np.abs(g[1] / g[0]).max(), np.abs(g[2] / g[0]).max())
+    say("lake velocity", vel, "surface", np.abs(g[0] + sc.b - eta0).max())
+    assert vel <= 1e-4 * c and np.abs(g[0] + sc.b - eta0).max() <= 5e-5
+
+
+def test_every_tile_variant_and_the_transpose_bitwise():
+    sc = inputs.random_wet(100, 37, seed=78, dry_fraction=0.1, manning=0.05)
+    ref = None
+    for tv in swe.tile_variants():
+        g, _ = gpu_run(sc, 4, tile=tv["index"])
+        if ref is None:
+            ref = g
+        assert all(np.array_equal(a, b) for a, b in zip(g, ref)), tv
+    (h, hu, hv), a = gpu_run(sc, 4)
+    (hT, huT, hvT), b = gpu_run(inputs.transpose(sc), 4)
+    assert np.array_equal(hT, h.T) and np.array_equal(huT, hv.T) and np.array_equal(hvT, hu.T)
+    assert a["t"] == b["t"]
+
+
+def test_large_coast_first_steps_against_checker():
+    # the 4096^2 coastline, 10 steps, autotuned tile and graph replays of 5
+    # steps (the bench's launch configuration for this option)
+    coast = inputs.large_coast()
+    tile, _ = swe.autotune(coast.params.nx, coast.params.ny)
+    g, st = gpu_run(coast, 10, tile=tile, graph_steps=5)
+    say("gpu done; checker 10 steps on the host", st)
+    r, rs = checker_run(coast, 10)
+    assert_front_parity(g, r, TOL_SMOOTH, "coast 4096^2, local split, 10 steps")
+    assert_epilogue_parity(st, rs, coast, "coast 4096^2, local split")
+    assert abs(st["t"] - rs["t"]) <= 1e-6 * rs["t"]

@@ -165,3 +165,29 @@ def test_served_maximum_depth_maps_equal_alone(mode):
     # the map's plane is part of the footprint: nothing stays allocated
     assert sv.stats()["mem_in_use"] == 0
     sv.close()
+
+
+def test_compensated_requests_equal_compensated_contexts():
+    # SWE_OPT_COMPENSATED on a server (before the first submit): every
+    # request's footprint carries its residual planes and the result equals a
+    # context with the option, bitwise; after a submit the option is fixed
+    mix = [(inputs.random_wet(64, 48, seed=21, dry_fraction=0.05), 13), (inputs.dam_break(nx=128, ny=64), 20)]
+    sv = swe.Server(mem_budget=256 << 20, max_slots=8, segment_steps=5)
+    sv.set_option(swe.OPT_COMPENSATED, 1)
+    tickets = [sv.submit_scenario(sc, n) for sc, n in mix]
+    with pytest.raises(swe.SweError) as ei:
+        sv.set_option(swe.OPT_COMPENSATED, 0)
+    assert ei.value.code == swe.EBUSY
+    res = wait_all(sv, tickets)
+    for t, (sc, n) in zip(tickets, mix):
+        r, state = res[t]
+        assert r["status"] == swe.DONE
+        s = swe.Solver.from_scenario(sc)
+        s.set_option(swe.OPT_TILE, 1)
+        s.set_option(swe.OPT_COMPENSATED, 1)
+        s.step(n)
+        ref = s.read()
+        s.close()
+        for a, b in zip(state, ref[:3]):
+            assert np.array_equal(a, b), sc.name
+    sv.close()
