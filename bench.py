@@ -16,11 +16,16 @@ Extra objects on the same JSON line:
                 the host and the maximum-depth map kept: cost per step and
                 how long after the run the last snapshot is on the host;
   batched       the mitigation ensemble (64 x 1024^2, dx 2 m, 3000 steps,
-                seeded hills and Manning patches) in one batch: scenarios/hour
-                batched vs the plain single-scenario solver, runup;
-  serving       Poisson arrivals of ensemble-sized requests at 0.7x the
-                measured batched capacity: p50/p99 time-to-result,
-                scenarios/hour, device-memory high-water mark.
+                Carrier's N-wave on a beach with seeded hills and Manning
+                patches) in one batch: scenarios/hour batched vs the plain
+                single-scenario solver, per-member runup;
+  uneven        200 scenarios of {256^2, 512x1024, 1024^2, 2048x1024} cells
+                and U{1000..4000} steps in one batch: scenarios/hour against
+                the plain solver one scenario at a time;
+  serving       Poisson arrivals of 500 requests with the uneven batch's size
+                and step mix at 0.7x and 1.0x of its measured batched
+                capacity, under a device-memory budget: p50/p99
+                time-to-result, scenarios/hour, memory high-water mark.
 """
 import argparse
 import hashlib
@@ -39,12 +44,14 @@ UNIT = "cell-RK3-updates/s"
 # u^n (3 planes) + b + g n^2 and writes u^(1) (3); stages 2 and 3 also read
 # u^n (3) for the RK combination: 32, 44, 44 bytes.
 BYTES_STAGE = (32.0, 44.0, 44.0)
-# Algorithmic flops per cell per stage, counted on the definition (each
-# add, mul, div, sqrt, pow once): two directions of split fluxes (2 x 25),
-# one face per direction of six WENO5-JS reconstructions (6 x 70) plus the
-# flux sum (3) and the bed-face value (48), divergence and bed term (2 x 10),
-# sources and assembly (16), RK combination (15), wave speeds (7).
-FLOPS_STAGE = 2 * 25 + 2 * (6 * 70 + 3 + 48 + 10) + 16 + 15 + 7
+# Algorithmic flops per cell per stage: 2.8e3 per cell-RK3-update (twelve
+# WENO5 reconstructions of ~65 flops per cell and stage, four bed-face
+# reuses, fluxes, splits, divergence, sources and the RK combination), a
+# third of it per stage launch.  A count on the definition (each add, mul,
+# div, sqrt, pow once) gives 1050 per stage, FLOPS_STAGE_DEF; the roofline
+# uses the smaller figure.
+FLOPS_STAGE = 2.8e3 / 3.0
+FLOPS_STAGE_DEF = 2 * 25 + 2 * (6 * 70 + 3 + 48 + 10) + 16 + 15 + 7
 HBM_PEAK = 8.0e12        # B/s
 # FP32 vector peak: 256 CU x 2.4 GHz x 128 FMA lanes per CU and clock x 2.
 # Plain (unpacked) v_fma_f32 streams sustain 1.5 wave64 instructions per CU
@@ -180,6 +187,7 @@ def run_large(args, torch, inputs, swe):
     s.set_option(swe.OPT_GRAPH_STEPS, args.graph_steps)
     s.set_option(swe.OPT_COMPENSATED, int(args.compensated))
     s.set_option(swe.OPT_FRICTION_IMPLICIT, int(args.friction_implicit))
+    s.set_option(swe.OPT_LOCAL_SPLIT, int(args.local_split))
     s.step(args.warmup)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
@@ -208,12 +216,13 @@ def run_large(args, torch, inputs, swe):
     ach_fl = flops_launch / (avg_ms * 1e-3)
     tv = swe.tile_variants()[tile]
     # counters were taken for the default kernels only
-    plain = not (args.compensated or args.friction_implicit)
+    plain = not (args.compensated or args.friction_implicit or args.local_split)
     traffic = measured_traffic(sc.name, (tv["tx"], tv["ty"], tv["r"])) if plain else None
     roof_alu = {"bound": "alu", "achieved": ach_fl / 1e12, "peak": FP32_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": ach_fl / FP32_PEAK, "traffic": traffic,
                 "kernel": "k_stage (3 stage launches per step)", "kernel_ms": kms,
-                "flops_per_cell_launch": FLOPS_STAGE}
+                "flops_per_cell_launch": FLOPS_STAGE,
+                "frac_with_definition_count": n * FLOPS_STAGE_DEF / (avg_ms * 1e-3) / FP32_PEAK}
     roof_hbm = {"bound": "hbm", "achieved": ach_bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": ach_bw / HBM_PEAK, "traffic": traffic,
                 "bytes_per_cell_launch": bytes_cell}
@@ -352,13 +361,15 @@ def run_batched(args, torch, inputs, swe):
     cells = 1024 * 1024
     out = {"workload": f"mitigation_ensemble_{len(members)}x1024x1024_dx2", "scenarios": len(members),
            "steps_per_scenario": args.ens_steps}
-    modes = [("rounds_graph", swe.BATCH_ROUNDS, True), ("persistent", swe.BATCH_PERSISTENT, False)]
+    known = {"rounds_graph": (swe.BATCH_ROUNDS, True), "rounds": (swe.BATCH_ROUNDS, False),
+             "persistent": (swe.BATCH_PERSISTENT, False)}
+    modes = [(m,) + known[m] for m in args.ens_modes]
     for name, mode, graph in modes:
         bt = swe.Batch()
         bt.set_mode(mode, graph)
         for sc in members:
             bt.add_scenario(sc)
-        steps = args.ens_steps if name == "rounds_graph" else min(args.ens_steps, 300)
+        steps = args.ens_steps if name == "rounds_graph" else min(args.ens_steps, args.ens_other_steps)
         torch.cuda.synchronize()
         t = time.perf_counter()
         bt.run(steps)
@@ -374,6 +385,8 @@ def run_batched(args, torch, inputs, swe):
                               "max": max(runups)}
         log(f"batched {name}: {steps} steps in {dt:.2f}s, {rate:.3e} cell-updates/s")
         bt.close()
+    if "scenarios_per_hour" not in out:
+        return out, members
     # plain single-scenario solver, one scenario at a time (same inputs, same steps)
     k = min(2, len(members))
     t = time.perf_counter()
@@ -390,50 +403,75 @@ def run_batched(args, torch, inputs, swe):
     return out, members
 
 
-def run_serving(args, swe, members, capacity_per_s):
-    """Poisson arrivals at 0.7x the batched capacity; time-to-result percentiles."""
+def run_serving(swe, scens, steps, rate, budget_bytes, max_slots, seed=5, label=""):
+    """Poisson arrivals at `rate` requests/s; request i is scenario
+    scens[i % len(scens)] run for steps[i] steps.  Returns time-to-result
+    percentiles, scenarios/hour and the memory high-water mark."""
     import numpy as np
-    rng = np.random.Generator(np.random.PCG64(5))
-    n = args.serve_requests
-    steps = rng.integers(args.serve_steps // 2, args.serve_steps * 3 // 2 + 1, size=n)
-    mean_steps = float(np.mean(steps))
-    rate = 0.7 * capacity_per_s * args.ens_steps / mean_steps  # requests per second
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = len(steps)
     gaps = rng.exponential(1.0 / rate, size=n)
-    sv = swe.Server(mem_budget=args.serve_budget_gb << 30, max_slots=args.serve_slots, segment_steps=100)
+    sv = swe.Server(mem_budget=budget_bytes, max_slots=max_slots, segment_steps=100)
     sv.set_mode(swe.BATCH_ROUNDS)
     t_start = time.perf_counter()
     t_next = t_start
     pending, results = {}, []
-    for i in range(n):
-        t_next += gaps[i]
-        while time.perf_counter() < t_next:
-            for tk in list(pending):
-                r, _ = sv.poll(tk, want_state=False)
-                if r["status"] != swe.PENDING:
-                    results.append(r)
-                    del pending[tk]
-            time.sleep(0.001)
-        sc = members[i % len(members)]
-        pending[sv.submit_scenario(sc, int(steps[i]))] = i
-    while pending:
+    t_log = t_start
+
+    def drain():
         for tk in list(pending):
             r, _ = sv.poll(tk, want_state=False)
             if r["status"] != swe.PENDING:
                 results.append(r)
                 del pending[tk]
+
+    for i in range(n):
+        t_next += gaps[i]
+        while time.perf_counter() < t_next:
+            drain()
+            time.sleep(0.001)
+        sc = scens[i % len(scens)]
+        pending[sv.submit_scenario(sc, int(steps[i]))] = i
+        if time.perf_counter() - t_log > 20.0:
+            t_log = time.perf_counter()
+            log(f"serving {label}: {i + 1}/{n} submitted, {len(results)} done")
+    while pending:
+        drain()
         time.sleep(0.002)
     st = sv.stats()
     sv.close()
     ok = [r for r in results if r["status"] == swe.DONE]
     ttr = np.array([r["t_done"] - r["t_submit"] for r in ok])
+    wait = np.array([r["t_admit"] - r["t_submit"] for r in ok])
     span = max(r["t_done"] for r in ok) - min(r["t_submit"] for r in ok)
-    return {"workload": "poisson_requests_1024x1024_dx2", "requests": n, "completed": len(ok),
-            "arrival_rate_per_s": rate, "steps_per_request": [int(steps.min()), int(steps.max())],
+    return {"requests": n, "completed": len(ok), "arrival_rate_per_s": rate,
+            "steps_per_request": [int(min(steps)), int(max(steps))],
             "p50_time_to_result_s": float(np.percentile(ttr, 50)),
             "p99_time_to_result_s": float(np.percentile(ttr, 99)),
+            "p50_admission_wait_s": float(np.percentile(wait, 50)),
+            "p99_admission_wait_s": float(np.percentile(wait, 99)),
             "scenarios_per_hour": len(ok) / span * 3600.0,
             "mem_budget_bytes": st["mem_budget"], "mem_high_water_bytes": st["mem_high_water"],
-            "max_slots": args.serve_slots, "segments": st["segments"]}
+            "budget_binds": bool(st["mem_high_water"] >= 0.9 * st["mem_budget"]),
+            "max_slots": max_slots, "segments": st["segments"]}
+
+
+def run_serving_mix(args, swe, scens, plan, capacity_per_s):
+    """Serving with the uneven batch's size and step mix: Poisson arrivals
+    at each of args.serve_loads times the measured batched capacity."""
+    n = args.serve_requests
+    steps = [plan[i % len(plan)][1] for i in range(n)]
+    out = {"workload": f"poisson_requests_uneven_mix_{n}", "capacity_scenarios_per_s": capacity_per_s,
+           "mix": "sizes and steps of the uneven batch, request i = scenario i mod %d" % len(plan)}
+    for frac in args.serve_loads:
+        res = run_serving(swe, scens, steps, frac * capacity_per_s, args.serve_budget_gb << 30,
+                          args.serve_slots, label=f"{frac}x")
+        res["load_fraction"] = frac
+        out[f"load_{frac}"] = res
+        log(f"serving at {frac}x capacity: p50 {res['p50_time_to_result_s']:.2f}s "
+            f"p99 {res['p99_time_to_result_s']:.2f}s, {res['scenarios_per_hour']:.0f} scenarios/hour, "
+            f"high water {res['mem_high_water_bytes'] / 1e9:.2f} GB")
+    return out
 
 
 def run_uneven(args, torch, inputs, swe):
@@ -456,11 +494,19 @@ def run_uneven(args, torch, inputs, swe):
         tiles[f"{nx}x{ny}"] = swe.autotune(nx, ny)[0]
     log(f"uneven: {len(plan)} scenarios ready in {time.perf_counter() - t0:.1f}s, tuned tiles {tiles}")
     out = {"workload": f"uneven_batch_{len(plan)}", "scenarios": len(plan), "cell_updates": cells_steps,
+           "tile_forced": args.uneven_tile, "compensated": bool(args.uneven_compensated),
            "sizes": {f"{nx}x{ny}": len(v) for (nx, ny), v in by_size.items()},
            "tuned_tile_variants": tiles}
-    for name, mode in (("rounds_graph", swe.BATCH_ROUNDS), ("persistent_graph", swe.BATCH_PERSISTENT)):
+    modes = [("rounds_graph", swe.BATCH_ROUNDS)]
+    if args.uneven_persistent:
+        modes.append(("persistent_graph", swe.BATCH_PERSISTENT))
+    for name, mode in modes:
         bt = swe.Batch()
         bt.set_mode(mode, True)
+        if args.uneven_tile >= 0:
+            bt.set_tile(args.uneven_tile)
+        if args.uneven_compensated:
+            bt.set_option(swe.OPT_COMPENSATED, 1)
         for sc in scens:
             bt.add_scenario(sc)
         torch.cuda.synchronize()
@@ -474,18 +520,18 @@ def run_uneven(args, torch, inputs, swe):
         out[name] = {"seconds": dt, "cell_updates_per_s": cells_steps / dt,
                      "scenarios_per_hour": len(plan) / dt * 3600.0}
         log(f"uneven {name}: {dt:.1f}s, {cells_steps / dt:.3e} cell-updates/s")
-    best = max(("rounds_graph", "persistent_graph"), key=lambda k: out[k]["scenarios_per_hour"])
+    best = max([m for m, _ in modes], key=lambda k: out[k]["scenarios_per_hour"])
     out["mode"] = best
     out["seconds"] = out[best]["seconds"]
     out["cell_updates_per_s"] = out[best]["cell_updates_per_s"]
     out["scenarios_per_hour"] = out[best]["scenarios_per_hour"]
-    # plain solver, one scenario at a time with its size's tuned tile: two
-    # members of each size class, the class's per-cell-update rate applied to
-    # all of its members
+    # plain solver, one scenario at a time with its size's tuned tile: the
+    # first member of each size class, the class's per-cell-update rate
+    # applied to all of its members
     plain_s = 0.0
     for (nx, ny), members in by_size.items():
         rates = []
-        for s_idx, steps in members[:2]:
+        for s_idx, steps in members[:1]:
             sol = swe.Solver.from_scenario(scens[s_idx])
             sol.stats()
             t = time.perf_counter()
@@ -499,32 +545,7 @@ def run_uneven(args, torch, inputs, swe):
     out["plain_solver_seconds_est"] = plain_s
     out["plain_solver_scenarios_per_hour"] = len(plan) / plain_s * 3600.0
     out["batched_over_plain"] = out["scenarios_per_hour"] / out["plain_solver_scenarios_per_hour"]
-    return out
-
-
-def run_serving_scale(args, torch, inputs, swe):
-    members = inputs.mitigation_ensemble(args.ens_count, 1024, 1024, 3000)
-    # capacity: a batch of the same size mix and steps, as in the ensemble run
-    bt = swe.Batch()
-    for sc in members:
-        bt.add_scenario(sc, 300)
-    bt.run(20)
-    bt.stats(0)
-    t = time.perf_counter()
-    bt.run()
-    bt.stats(0)
-    dt = time.perf_counter() - t
-    bt.close()
-    cap = len(members) * 280 / dt  # scenario-steps per second / steps
-    out = {"capacity_scenario_steps_per_s": cap}
-    for frac in args.serve_loads:
-        a = argparse.Namespace(**vars(args))
-        a.ens_steps = 1
-        res = run_serving(a, swe, members, cap * frac / 0.7)
-        res["load_fraction"] = frac
-        out[f"load_{frac}"] = res
-        log(f"serving at {frac}: p50 {res['p50_time_to_result_s']:.2f}s p99 {res['p99_time_to_result_s']:.2f}s")
-    return out
+    return out, scens, plan
 
 
 def main():
@@ -538,27 +559,41 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--no-batched", action="store_true", help="skip the ensemble and serving runs")
+    ap.add_argument("--no-batched", action="store_true", help="skip the ensemble run")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven batch (and the serving run)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--uneven-persistent", action="store_true",
+                    help="also run the uneven batch with the persistent kernel")
     ap.add_argument("--no-outputs", action="store_true", help="skip the snapshot/max-depth measurement")
     ap.add_argument("--no-end-to-end", action="store_true",
                     help="skip the host-to-host run (create from host fields, steps, read to host)")
     ap.add_argument("--no-small-grid", action="store_true", help="skip the 128 x 64 latency measurement")
     ap.add_argument("--ens-count", type=int, default=64)
     ap.add_argument("--ens-steps", type=int, default=3000)
-    ap.add_argument("--serve-requests", type=int, default=48)
-    ap.add_argument("--serve-steps", type=int, default=1000)
+    ap.add_argument("--ens-modes", nargs="+", default=["rounds_graph", "persistent"],
+                    choices=["rounds_graph", "rounds", "persistent"],
+                    help="launch modes of the ensemble run (rounds_graph gives scenarios/hour)")
+    ap.add_argument("--ens-other-steps", type=int, default=300,
+                    help="steps of the ensemble run in modes other than rounds_graph")
+    ap.add_argument("--serve-requests", type=int, default=500)
     ap.add_argument("--serve-budget-gb", type=int, default=2)
     ap.add_argument("--serve-slots", type=int, default=64,
                     help="requests resident and stepped together (the server's max_slots)")
     ap.add_argument("--workload", choices=("coast", "uneven", "serving"), default="coast",
-                    help="coast: the main line (default); uneven: the 200-scenario uneven batch; "
-                         "serving: Poisson serving at --serve-loads of capacity")
+                    help="coast: every line (default); uneven: the 200-scenario uneven batch alone; "
+                         "serving: the uneven batch, then Poisson serving at --serve-loads of its capacity")
     ap.add_argument("--uneven-count", type=int, default=200)
+    ap.add_argument("--uneven-tile", type=int, default=-1,
+                    help="tile variant of the uneven batch's launches (-1: the one tuned for its largest size)")
+    ap.add_argument("--uneven-compensated", action="store_true",
+                    help="the uneven batch with the compensated level (SWE_OPT_COMPENSATED)")
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.7, 1.0])
     ap.add_argument("--compensated", action="store_true",
                     help="main line with the compensated level (SWE_OPT_COMPENSATED)")
     ap.add_argument("--friction-implicit", action="store_true",
                     help="main line with point-implicit friction (SWE_OPT_FRICTION_IMPLICIT)")
+    ap.add_argument("--local-split", action="store_true",
+                    help="main line with local Lax-Friedrichs splitting (SWE_OPT_LOCAL_SPLIT)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -572,11 +607,12 @@ def main():
     from paper_2301_12010_amd import inputs, swe
 
     torch.cuda.set_device(0)
-    if args.workload == "uneven":
-        print(json.dumps(run_uneven(args, torch, inputs, swe)), flush=True)
-        return
-    if args.workload == "serving":
-        print(json.dumps(run_serving_scale(args, torch, inputs, swe)), flush=True)
+    if args.workload in ("uneven", "serving"):
+        res, scens, plan = run_uneven(args, torch, inputs, swe)
+        out = {"uneven": res}
+        if args.workload == "serving":
+            out["serving"] = run_serving_mix(args, swe, scens, plan, res["scenarios_per_hour"] / 3600.0)
+        print(json.dumps(out), flush=True)
         return
     sc, value, ms, roofline, other, tv, outputs, e2e = run_large(args, torch, inputs, swe)
     out = {
@@ -589,9 +625,10 @@ def main():
                    "tile": [tv["tx"], tv["ty"], tv["r"]], "graph_steps": args.graph_steps},
         "roofline": roofline, "roofline_other": other,
     }
-    if args.compensated or args.friction_implicit:
+    if args.compensated or args.friction_implicit or args.local_split:
         out["config"]["options"] = {"compensated": bool(args.compensated),
-                                    "friction": "implicit" if args.friction_implicit else "explicit"}
+                                    "friction": "implicit" if args.friction_implicit else "explicit",
+                                    "split": "local" if args.local_split else "global"}
     if e2e is not None:
         out["end_to_end"] = e2e
     if outputs is not None:
@@ -601,10 +638,14 @@ def main():
     if not args.no_batched:
         batched, members = run_batched(args, torch, inputs, swe)
         out["batched"] = batched
-        cap = batched["scenarios_per_hour"] / 3600.0
-        log(f"serving {args.serve_requests} requests ...")
-        out["serving"] = run_serving(args, swe, members, cap)
         del members
+    if not args.no_uneven:
+        uneven, scens, plan = run_uneven(args, torch, inputs, swe)
+        out["uneven"] = uneven
+        if not args.no_serving:
+            log(f"serving {args.serve_requests} requests at {args.serve_loads} of the uneven capacity ...")
+            out["serving"] = run_serving_mix(args, swe, scens, plan, uneven["scenarios_per_hour"] / 3600.0)
+        del scens
     if args.calibrate_copy_mb > 0:
         n = args.calibrate_copy_mb * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")
