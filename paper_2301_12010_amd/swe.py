@@ -387,7 +387,9 @@ def use_torch_allocator(enable: bool = True):
 
 
 class Batch:
-    """Many scenarios advanced together by one persistent launch per run."""
+    """Many scenarios advanced together: by default one launch per stage
+    round over every active scenario, captured as one hipGraph per run;
+    set_mode selects the persistent launch instead."""
 
     def __init__(self, stream=None):
         out = _VP()
