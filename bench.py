@@ -25,7 +25,9 @@ Extra objects on the same JSON line:
   serving       Poisson arrivals of 500 requests with the uneven batch's size
                 and step mix at 0.7x and 1.0x of its measured batched
                 capacity, under a device-memory budget: p50/p99
-                time-to-result, scenarios/hour, memory high-water mark.
+                time-to-result, scenarios/hour, memory high-water mark;
+  valu_calibration  the vector-ALU issue ceiling for unpacked FP32 code,
+                measured on the same GPU (the stage kernel's roofline).
 """
 import argparse
 import hashlib
@@ -53,15 +55,52 @@ BYTES_STAGE = (32.0, 44.0, 44.0)
 FLOPS_STAGE = 2.8e3 / 3.0
 FLOPS_STAGE_DEF = 2 * 25 + 2 * (6 * 70 + 3 + 48 + 10) + 16 + 15 + 7
 HBM_PEAK = 8.0e12        # B/s
-# FP32 vector peak: 256 CU x 2.4 GHz x 128 FMA lanes per CU and clock x 2.
-# Plain (unpacked) v_fma_f32 streams sustain 1.5 wave64 instructions per CU
-# and clock on the MI355X (above the 1.0 a 64-lane-per-clock CU would allow),
-# so the published figure, not half of it, is the ceiling for unpacked code.
+# FP32 vector peak as published: 256 CU x 2.4 GHz x 128 FMA lanes per CU
+# and clock x 2 flops; the 128 lanes count packed FP32 (two FMAs per lane in
+# one v_pk_fma_f32).  All device code here is built with packed FP32
+# disabled, so the ceiling for the code that runs is half of it: 64 FMA lanes
+# per CU and clock, one wave64 VALU instruction per CU and clock, 78.6
+# TFLOP/s (the valu_calibration object measures it live; transcendental
+# instructions such as v_rcp_f32 take two issue cycles).
 FP32_PEAK = 157.3e12
+FP32_UNPACKED_PEAK = 256 * 2.4e9 * 64 * 2
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def valu_calibration(iters=4096):
+    """Vector-ALU issue ceiling of the GPU for the code this library builds
+    (libswe_calib.so): wave64 VALU instructions per CU and clock, at the
+    nominal 2.4 GHz, of 16 independent chains per thread of two FMAs
+    ("fma"), one v_rcp_f32 and one FMA ("rcp_fma") and one v_rcp_f32 and
+    seven FMAs ("rcp_7fma"), at 1, 2, 4 and 8 waves per SIMD."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2301_12010_amd", "libswe_calib.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    lib.swe_calib_valu.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)]
+    lib.swe_calib_valu.restype = ctypes.c_int
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {"clock_ghz_assumed": 2.4, "cus": cus}
+    for op, name in enumerate(("fma", "rcp_fma", "rcp_7fma")):
+        rates = {}
+        for w in (1, 2, 4, 8):
+            ms, wi = ctypes.c_float(), ctypes.c_double()
+            rc = lib.swe_calib_valu(op, w, iters, ctypes.byref(ms), ctypes.byref(wi))
+            if rc != 0:
+                raise RuntimeError(f"swe_calib_valu({op}, {w}) failed: {rc}")
+            rates[str(w)] = wi.value / (cus * ms.value * 1e-3 * 2.4e9)
+        out[name] = rates
+    # issue cycles of one v_rcp_f32 in units of one FMA's, from the 8-wave rates
+    f, r1 = out["fma"]["8"], out["rcp_fma"]["8"]
+    out["rcp_issue_cycles_per_fma"] = (2.0 / r1 - 1.0 / f) * f
+    log(f"VALU calibration: fma {f:.3f}, rcp+fma {r1:.3f} wave64 instr per CU per clock at 8 waves/SIMD")
+    return out
 
 
 def kernel_source_digest(text=None):
@@ -222,7 +261,8 @@ def run_large(args, torch, inputs, swe):
                 "unit": "TFLOP/s", "frac": ach_fl / FP32_PEAK, "traffic": traffic,
                 "kernel": "k_stage (3 stage launches per step)", "kernel_ms": kms,
                 "flops_per_cell_launch": FLOPS_STAGE,
-                "frac_with_definition_count": n * FLOPS_STAGE_DEF / (avg_ms * 1e-3) / FP32_PEAK}
+                "frac_with_definition_count": n * FLOPS_STAGE_DEF / (avg_ms * 1e-3) / FP32_PEAK,
+                "peak_unpacked": FP32_UNPACKED_PEAK / 1e12, "frac_unpacked": ach_fl / FP32_UNPACKED_PEAK}
     roof_hbm = {"bound": "hbm", "achieved": ach_bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": ach_bw / HBM_PEAK, "traffic": traffic,
                 "bytes_per_cell_launch": bytes_cell}
@@ -594,6 +634,8 @@ def main():
                     help="main line with point-implicit friction (SWE_OPT_FRICTION_IMPLICIT)")
     ap.add_argument("--local-split", action="store_true",
                     help="main line with local Lax-Friedrichs splitting (SWE_OPT_LOCAL_SPLIT)")
+    ap.add_argument("--no-valu-calibration", action="store_true",
+                    help="skip the vector-ALU issue calibration (libswe_calib.so)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -646,6 +688,8 @@ def main():
             log(f"serving {args.serve_requests} requests at {args.serve_loads} of the uneven capacity ...")
             out["serving"] = run_serving_mix(args, swe, scens, plan, uneven["scenarios_per_hour"] / 3600.0)
         del scens
+    if not args.no_valu_calibration:
+        out["valu_calibration"] = valu_calibration()
     if args.calibrate_copy_mb > 0:
         n = args.calibrate_copy_mb * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")

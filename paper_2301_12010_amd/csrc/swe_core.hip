@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256) void k_init(Geo G)
         const float b = G.b[gi], lo = fminf(b, 0.f);
         const float h = G.U[0][gi] - lo, hu = G.U[1][gi], hv = G.U[2][gi];
         const bool wet = h > G.h_dry;
-        const float cel = sqrtf(G.g * fmaxf(h, 0.f));
+        const float cel = fsqrt(G.g * fmaxf(h, 0.f));
         const float inv = wet ? 1.f / h : 0.f;
         const bool fin = fabsf(h) <= 3.4e38f && fabsf(hu) <= 3.4e38f && fabsf(hv) <= 3.4e38f;
         const unsigned int bx = fin ? speed_bits(fabsf(hu * inv) + cel) : 0x7f800000u;

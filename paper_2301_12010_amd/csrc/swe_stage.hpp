@@ -93,6 +93,10 @@ __device__ __forceinline__ int ghost_index(const Geo &G, int side, int field, in
 }
 
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// Hardware square root (v_sqrt_f32, within 1 ulp; no correctly-rounded
+// expansion, which costs about ten more instructions).  It only enters wave
+// speeds and the friction's |q|, whose results the FP64 checker bounds.
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Error-free sum (Knuth): s + e == a + b exactly, s = fl(a + b).
 __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
@@ -428,7 +432,7 @@ __device__ __forceinline__ void sweep_llf(const float *__restrict__ Ls, const fl
         wu[5][1] = hu;
         wu[5][2] = hv;
         wb[5] = b;
-        ws[5] = fabsf(un) + sqrtf(K.g * fmaxf(h, 0.f));
+        ws[5] = fabsf(un) + fsqrt(K.g * fmaxf(h, 0.f));
         if (w >= 0 && w < R) eta[w >= 0 && w < R ? w : 0] = sv;
         if (w < 2) continue;
         const int f = w - 2;  // face between cells f-1 and f: its window is complete
@@ -747,7 +751,7 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
         if (h > h_dry && gn2 > 0.f) {
             // |q| as a sum of two rounded squares: the same for (hu, hv) and
             // (hv, hu), so the step commutes with exchanging x and y
-            const float qn = sqrtf(hu * hu + hv * hv);
+            const float qn = fsqrt(hu * hu + hv * hv);
             const float hm73 = __builtin_amdgcn_exp2f(-2.33333333333333f * __builtin_amdgcn_logf(h));
             if (IMP) {
                 kimp = gn2 * qn * hm73;
@@ -840,12 +844,16 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
             // maximum-depth map over the states after completed steps
             if (oh > pld(G.hmax, gi)) pst(G.hmax, gi, oh);
         }
-        // wave speeds of the output (the next stage's input)
-        const float cel = sqrtf(G.g * oh);
+        // wave speeds of the output (the next stage's input), as float bits:
+        // a speed is +0 or more, so its bits order as unsigned integers, and a
+        // non-finite output gives an infinite or NaN speed (a NaN depth fails
+        // the wet test and leaves cel NaN; an infinite momentum meets inv = 0
+        // or a finite inv), whose bits are 0x7f800000 or above; the block
+        // reduction clamps those to the bits of +inf
+        const float cel = fsqrt(G.g * oh);
         const float inv = wet ? frcp(oh) : 0.f;
-        const bool fin = fabsf(oh) <= 3.4e38f && fabsf(ohu) <= 3.4e38f && fabsf(ohv) <= 3.4e38f;
-        const unsigned int bx = fin ? speed_bits(fabsf(ohu * inv) + cel) : 0x7f800000u;
-        const unsigned int by = fin ? speed_bits(fabsf(ohv * inv) + cel) : 0x7f800000u;
+        const unsigned int bx = __float_as_uint(fabsf(ohu * inv) + cel);
+        const unsigned int by = __float_as_uint(fabsf(ohv * inv) + cel);
         acc.sxb = bx > acc.sxb ? bx : acc.sxb;
         acc.syb = by > acc.syb ? by : acc.syb;
         if (STAGE == 3) {
@@ -872,8 +880,10 @@ __device__ __forceinline__ void stage_publish(const Geo &G, const StageScalars &
     const int STAGE = sc.stage;
     DevScen *sd = G.sd;
     const int tid = threadIdx.x;
-    unsigned int sxb = wave_max_u32(acc.sxb);
-    unsigned int syb = wave_max_u32(acc.syb);
+    // NaN bits (above those of +inf) become +inf, the value a non-finite
+    // speed publishes
+    unsigned int sxb = min(wave_max_u32(acc.sxb), 0x7f800000u);
+    unsigned int syb = min(wave_max_u32(acc.syb), 0x7f800000u);
     const bool any_def = __any(acc.deficit > 0.f);
     double dsum = any_def ? wave_sum_f64((double)acc.deficit) : 0.0;
     unsigned int rub = STAGE == 3 ? wave_max_u32(acc.rub) : 0u;

@@ -116,3 +116,21 @@ def test_checker_library_exports():
     for n in ("oracle_create", "oracle_step", "oracle_read", "oracle_scalars", "oracle_rhs",
               "oracle_weno5", "oracle_destroy"):
         assert hasattr(L, n)
+
+
+def test_calibration_library_exports_and_rejects_bad_arguments():
+    # the benchmark's vector-ALU calibration: a library of its own, outside
+    # the solver's ABI; argument checks run before any GPU call
+    path = swe.LIB_PATH.parent / "libswe_calib.so"
+    if not path.exists():
+        pytest.fail("libswe_calib.so is not built")
+    L = ctypes.CDLL(str(path))
+    f = L.swe_calib_valu
+    f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
+                  ctypes.POINTER(ctypes.c_double)]
+    f.restype = ctypes.c_int
+    ms, wi = ctypes.c_float(), ctypes.c_double()
+    assert f(3, 2, 10, ctypes.byref(ms), ctypes.byref(wi)) == -1
+    assert f(0, 3, 10, ctypes.byref(ms), ctypes.byref(wi)) == -1
+    assert f(0, 2, 0, ctypes.byref(ms), ctypes.byref(wi)) == -1
+    assert f(0, 2, 10, None, ctypes.byref(wi)) == -1
