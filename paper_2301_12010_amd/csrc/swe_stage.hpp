@@ -97,6 +97,15 @@ __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x)
 // expansion, which costs about ten more instructions).  It only enters wave
 // speeds and the friction's |q|, whose results the FP64 checker bounds.
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+// min(x, 0) as one v_min_f32.  fminf on a value loaded from memory costs two
+// instructions in IEEE mode (the compiler first quiets a possible signalling
+// NaN); the bed values this takes are finite (checked at creation).
+__device__ __forceinline__ float min0(float x)
+{
+    float r;
+    asm("v_min_f32 %0, 0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
 
 // Error-free sum (Knuth): s + e == a + b exactly, s = fl(a + b).
 __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
@@ -203,7 +212,7 @@ __device__ __forceinline__ void sweep(const float *__restrict__ Ls, const float 
         // u~ = (sv, hu, hv) and the bed term's coefficient sv: the printed
         // (h + b) form below the datum, the depth form on land, where dry
         // cells then carry no flux at all
-        const float lo = fminf(b, 0.f);
+        const float lo = min0(b);
         const float h = sv - lo;
         const float inv = h > K.h_dry ? frcp(h) : 0.f;
         const float pres = K.half_g * (h - lo) * sv;
@@ -399,7 +408,7 @@ __device__ __forceinline__ void sweep_llf(const float *__restrict__ Ls, const fl
     for (int w = -HALO; w < R + HALO; ++w) {
         const int li = li0 + (w + HALO) * st;
         const float sv = Ls[li], hu = Lhu[li], hv = Lhv[li], b = Lb[li];
-        const float lo = fminf(b, 0.f);
+        const float lo = min0(b);
         const float h = sv - lo;
         const float inv = h > K.h_dry ? frcp(h) : 0.f;
         const float pres = K.half_g * (h - lo) * sv;
@@ -557,7 +566,15 @@ struct StagePartials {
 template <class C>
 struct TileRegs {
     static constexpr int NE = C::WX * C::WY;
-    static constexpr int IT = (NE + C::NT - 1) / C::NT;
+    static constexpr int IT_ANY = (NE + C::NT - 1) / C::NT;  // element rounds (edge tiles)
+    // interior tiles: passes over the first TX staged columns, RPI rows per
+    // pass (thread = (row q, column c)), then the 2 HALO last columns
+    static constexpr int RPI = C::NT / C::TX;
+    static constexpr int MI = (C::WY + RPI - 1) / RPI;
+    static constexpr int NR = 2 * HALO * C::WY;
+    static constexpr int RI = (NR + C::NT - 1) / C::NT;
+    static constexpr int IT = IT_ANY > MI + RI ? IT_ANY : MI + RI;
+    static_assert(C::NT % C::TX == 0, "whole rows of threads per pass");
     float h[IT], hu[IT], hv[IT], b[IT];
 };
 
@@ -581,7 +598,45 @@ __device__ __forceinline__ void tile_load(const Geo &G, int STAGE, int tx, int t
     const float *w0 = W[0], *w1 = W[1], *w2 = W[2];
     const int nx = G.nx, ny = G.ny, pitch = G.pitch;
     const int x0 = tx * C::TX, y0 = ty * C::TY;
-    constexpr int NE = TileRegs<C>::NE, IT = TileRegs<C>::IT;
+    using T = TileRegs<C>;
+    if (INNER) {
+        // every pass whose rows lie in the window reads at one per-thread
+        // offset from plane bases advanced by the pass's rows (uniform), so
+        // the loads need no per-load vector arithmetic; rows of a last,
+        // partial pass are clamped to the window's last row
+        const int c = threadIdx.x % C::TX, q = threadIdx.x / C::TX;
+        const unsigned off = (unsigned)((y0 - HALO + q) * pitch + x0 - HALO + c);
+#pragma unroll
+        for (int k = 0; k < T::MI; ++k) {
+            if ((k + 1) * T::RPI <= C::WY) {
+                const size_t adv = (size_t)(k * T::RPI) * (size_t)pitch;
+                v.h[k] = pld(w0 + adv, off);
+                v.hu[k] = pld(w1 + adv, off);
+                v.hv[k] = pld(w2 + adv, off);
+                v.b[k] = pld(G.b + adv, off);
+            } else {
+                const int r = q + k * T::RPI < C::WY ? q + k * T::RPI : C::WY - 1;
+                const unsigned i = (unsigned)((y0 - HALO + r) * pitch + x0 - HALO + c);
+                v.h[k] = pld(w0, i);
+                v.hu[k] = pld(w1, i);
+                v.hv[k] = pld(w2, i);
+                v.b[k] = pld(G.b, i);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < T::RI; ++j) {
+            int e = threadIdx.x + j * C::NT;
+            e = (T::RI * C::NT == T::NR || e < T::NR) ? e : T::NR - 1;
+            const int r = e / (2 * HALO), cc = C::TX + e % (2 * HALO);
+            const unsigned i = (unsigned)((y0 - HALO + r) * pitch + x0 - HALO + cc);
+            v.h[T::MI + j] = pld(w0, i);
+            v.hu[T::MI + j] = pld(w1, i);
+            v.hv[T::MI + j] = pld(w2, i);
+            v.b[T::MI + j] = pld(G.b, i);
+        }
+        return;
+    }
+    constexpr int NE = T::NE, IT = T::IT_ANY;
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         // spare threads of the last round restage the tile's last cell
@@ -590,17 +645,12 @@ __device__ __forceinline__ void tile_load(const Geo &G, int STAGE, int tx, int t
         e = (IT * C::NT == NE || e < NE) ? e : NE - 1;
         const int r = e / C::WX;
         const int cc = e - r * C::WX;
-        unsigned i;
-        if (INNER) {
-            i = (unsigned)((y0 - HALO + r) * pitch + x0 - HALO + cc);
-        } else {
-            const int gx = x0 - HALO + cc, gy = y0 - HALO + r;
-            int mx = gx < 0 ? -1 - gx : (gx >= nx ? 2 * nx - 1 - gx : gx);
-            int my = gy < 0 ? -1 - gy : (gy >= ny ? 2 * ny - 1 - gy : gy);
-            mx = mx < 0 ? 0 : (mx >= nx ? nx - 1 : mx);
-            my = my < 0 ? 0 : (my >= ny ? ny - 1 : my);
-            i = (unsigned)(my * pitch + mx);
-        }
+        const int gx = x0 - HALO + cc, gy = y0 - HALO + r;
+        int mx = gx < 0 ? -1 - gx : (gx >= nx ? 2 * nx - 1 - gx : gx);
+        int my = gy < 0 ? -1 - gy : (gy >= ny ? 2 * ny - 1 - gy : gy);
+        mx = mx < 0 ? 0 : (mx >= nx ? nx - 1 : mx);
+        my = my < 0 ? 0 : (my >= ny ? ny - 1 : my);
+        const unsigned i = (unsigned)(my * pitch + mx);
         v.h[it] = pld(w0, i);
         v.hu[it] = pld(w1, i);
         v.hv[it] = pld(w2, i);
@@ -616,7 +666,32 @@ __device__ __forceinline__ void tile_store(const Geo &G, int tx, int ty, const T
     float *Lh = lds, *Lhu = lds + C::PLANE, *Lhv = lds + 2 * C::PLANE, *Lb = lds + 3 * C::PLANE;
     const int nx = G.nx, ny = G.ny;
     const int x0 = tx * C::TX, y0 = ty * C::TY;
-    constexpr int NE = TileRegs<C>::NE, IT = TileRegs<C>::IT;
+    using T = TileRegs<C>;
+    if (INNER) {
+        // the pass layout of tile_load: one LDS index plus a constant per pass
+        const int c = threadIdx.x % C::TX, q = threadIdx.x / C::TX;
+#pragma unroll
+        for (int k = 0; k < T::MI; ++k) {
+            const int r = (k + 1) * T::RPI <= C::WY || q + k * T::RPI < C::WY ? q + k * T::RPI : C::WY - 1;
+            const int li = r * C::SX + c;
+            Lh[li] = v.h[k];
+            Lhu[li] = v.hu[k];
+            Lhv[li] = v.hv[k];
+            Lb[li] = v.b[k];
+        }
+#pragma unroll
+        for (int j = 0; j < T::RI; ++j) {
+            int e = threadIdx.x + j * C::NT;
+            e = (T::RI * C::NT == T::NR || e < T::NR) ? e : T::NR - 1;
+            const int li = (e / (2 * HALO)) * C::SX + C::TX + e % (2 * HALO);
+            Lh[li] = v.h[T::MI + j];
+            Lhu[li] = v.hu[T::MI + j];
+            Lhv[li] = v.hv[T::MI + j];
+            Lb[li] = v.b[T::MI + j];
+        }
+        return;
+    }
+    constexpr int NE = T::NE, IT = T::IT_ANY;
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         int e = threadIdx.x + it * C::NT;
@@ -624,13 +699,6 @@ __device__ __forceinline__ void tile_store(const Geo &G, int tx, int ty, const T
         const int r = e / C::WX;
         const int cc = e - r * C::WX;
         const int li = r * C::SX + cc;
-        if (INNER) {
-            Lh[li] = v.h[it];
-            Lhu[li] = v.hu[it];
-            Lhv[li] = v.hv[it];
-            Lb[li] = v.b[it];
-            continue;
-        }
         const int gx = x0 - HALO + cc, gy = y0 - HALO + r;
         const bool inx = (unsigned)gx < (unsigned)nx, iny = (unsigned)gy < (unsigned)ny;
         float h = v.h[it], hu = v.hu[it], hv = v.hv[it], b = v.b[it];
@@ -739,7 +807,7 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
         const int li = (ly + HALO) * C::SX + col + HALO;
         const int xi = ly * C::XR + col;
         const float sv = Ls[li], hu = Lhu[li], hv = Lhv[li], bb = Lb[li];
-        const float lo = fminf(bb, 0.f);  // level of zero depth
+        const float lo = min0(bb);  // level of zero depth
         const float h = sv - lo;
         float Lh_ = Xr[xi] + ry0;
         float Lhu_ = Xr[C::XPLANE + xi] + ry1;
