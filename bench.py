@@ -535,6 +535,7 @@ def run_uneven(args, torch, inputs, swe):
     log(f"uneven: {len(plan)} scenarios ready in {time.perf_counter() - t0:.1f}s, tuned tiles {tiles}")
     out = {"workload": f"uneven_batch_{len(plan)}", "scenarios": len(plan), "cell_updates": cells_steps,
            "tile_forced": args.uneven_tile, "compensated": bool(args.uneven_compensated),
+           "local_split": bool(args.uneven_local_split),
            "sizes": {f"{nx}x{ny}": len(v) for (nx, ny), v in by_size.items()},
            "tuned_tile_variants": tiles}
     modes = [("rounds_graph", swe.BATCH_ROUNDS)]
@@ -547,6 +548,8 @@ def run_uneven(args, torch, inputs, swe):
             bt.set_tile(args.uneven_tile)
         if args.uneven_compensated:
             bt.set_option(swe.OPT_COMPENSATED, 1)
+        if args.uneven_local_split:
+            bt.set_option(swe.OPT_LOCAL_SPLIT, 1)
         for sc in scens:
             bt.add_scenario(sc)
         torch.cuda.synchronize()
@@ -565,14 +568,16 @@ def run_uneven(args, torch, inputs, swe):
     out["seconds"] = out[best]["seconds"]
     out["cell_updates_per_s"] = out[best]["cell_updates_per_s"]
     out["scenarios_per_hour"] = out[best]["scenarios_per_hour"]
-    # plain solver, one scenario at a time with its size's tuned tile: the
-    # first member of each size class, the class's per-cell-update rate
-    # applied to all of its members
+    # plain solver, one scenario at a time with its size's tuned tile and the
+    # batch's options: the first member of each size class, the class's
+    # per-cell-update rate applied to all of its members
     plain_s = 0.0
     for (nx, ny), members in by_size.items():
         rates = []
         for s_idx, steps in members[:1]:
             sol = swe.Solver.from_scenario(scens[s_idx])
+            sol.set_option(swe.OPT_COMPENSATED, int(args.uneven_compensated))
+            sol.set_option(swe.OPT_LOCAL_SPLIT, int(args.uneven_local_split))
             sol.stats()
             t = time.perf_counter()
             sol.step(steps)
@@ -627,6 +632,8 @@ def main():
                     help="tile variant of the uneven batch's launches (-1: the one tuned for its largest size)")
     ap.add_argument("--uneven-compensated", action="store_true",
                     help="the uneven batch with the compensated level (SWE_OPT_COMPENSATED)")
+    ap.add_argument("--uneven-local-split", action="store_true",
+                    help="the uneven batch with local Lax-Friedrichs splitting (SWE_OPT_LOCAL_SPLIT)")
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.7, 1.0])
     ap.add_argument("--compensated", action="store_true",
                     help="main line with the compensated level (SWE_OPT_COMPENSATED)")

@@ -133,7 +133,7 @@ void swe_destroy(swe_ctx *ctx);
  * so that increments below half an ulp of the level are kept; removes the
  * FP32 mass drift of shallow wet/dry runs (up to 6e-10 of the mass per step
  * otherwise; about 1e-13 with it).  Costs 8-12 more bytes of traffic per
- * cell and stage and about 19% more time per step.  0 (default): off.  Can
+ * cell and stage and about 18% more time per step.  0 (default): off.  Can
  * be switched at any time (the residual then starts at zero; the captured
  * graph is dropped).  Returns SWE_EINVAL for other values, SWE_ENOMEM when
  * the planes cannot be allocated (the option is then off).  Batches take it
@@ -160,7 +160,8 @@ void swe_destroy(swe_ctx *ctx);
  * global.  Each face then reconstructs its own split values (no sharing
  * between neighbouring faces), about twice the arithmetic.  0 (default):
  * the global speed.  Can be switched at any time (the captured graph is
- * dropped); other values are SWE_EINVAL.  Contexts only. */
+ * dropped); other values are SWE_EINVAL.  Batches and servers take it
+ * through swe_batch_set_option and swe_server_set_option. */
 #define SWE_OPT_LOCAL_SPLIT 5
 int swe_set_option(swe_ctx *ctx, int32_t key, int64_t value);
 
@@ -294,7 +295,8 @@ int swe_batch_set_mode(swe_batch *bt, int32_t mode, int32_t use_graph);
 int swe_batch_set_tile(swe_batch *bt, int32_t tile);
 /* Batch options, 0 or 1, for every scenario of the batch from the next
  * swe_batch_run on: SWE_OPT_FRICTION_IMPLICIT (Methods, the friction variant
- * described at that key) and SWE_OPT_COMPENSATED (residual planes, 12 bytes
+ * described at that key), SWE_OPT_LOCAL_SPLIT (Methods, the splitting
+ * variant described at that key) and SWE_OPT_COMPENSATED (residual planes, 12 bytes
  * per cell, for every scenario present and added later; switching it on
  * starts the residuals at zero, off releases them).  A scenario then
  * advances bitwise as a context with the same options.  Other keys or values
@@ -380,8 +382,8 @@ int swe_poll_ex(swe_server *sv, uint64_t ticket, swe_result *r, float *h, float 
 /* Launch mode of the server's segments (SWE_BATCH_ROUNDS, the default, or
  * SWE_BATCH_PERSISTENT); takes effect at the next segment. */
 int swe_server_set_mode(swe_server *sv, int32_t mode);
-/* Server options, 0 or 1, for every request: SWE_OPT_FRICTION_IMPLICIT and
- * SWE_OPT_COMPENSATED (each request's footprint then includes its three
+/* Server options, 0 or 1, for every request: SWE_OPT_FRICTION_IMPLICIT,
+ * SWE_OPT_LOCAL_SPLIT and SWE_OPT_COMPENSATED (each request's footprint then includes its three
  * residual planes); settable before the first submit only (SWE_EBUSY after
  * it), so that all requests share one treatment.  Other keys or values are
  * SWE_EINVAL. */

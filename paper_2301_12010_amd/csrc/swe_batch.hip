@@ -59,11 +59,12 @@ SegmentLauncher::~SegmentLauncher()
 }
 
 int SegmentLauncher::run(const std::vector<Geo> &geos, const std::vector<int> &ksteps, int vi, int mode,
-                         bool use_graph, hipStream_t stream, bool implicit, bool compensated)
+                         bool use_graph, hipStream_t stream, bool implicit, bool compensated, bool local_split)
 {
     const Variant &v = variant(vi);
-    const BatchKernels &K = compensated ? (implicit ? g_bk_cmp_imp[vi] : g_bk_cmp[vi])
-                                        : (implicit ? g_bk_imp[vi] : g_bk[vi]);
+    static const BatchKernels *const sets[8] = {g_bk,     g_bk_cmp,     g_bk_imp,     g_bk_cmp_imp,
+                                                g_bk_llf, g_bk_llf_cmp, g_bk_llf_imp, g_bk_llf_cmp_imp};
+    const BatchKernels &K = sets[(compensated ? 1 : 0) + (implicit ? 2 : 0) + (local_split ? 4 : 0)][vi];
     const int n = (int)geos.size();
     std::vector<int> nxs(n), nys(n);
     for (int i = 0; i < n; ++i) {
@@ -192,6 +193,7 @@ struct swe_batch {
     int tile = -1;
     bool implicit = false;     // point-implicit friction
     bool compensated = false;  // compensated level (residual planes per scenario)
+    bool local_split = false;  // local Lax-Friedrichs splitting
     SegmentLauncher seg;
 };
 
@@ -283,6 +285,10 @@ int swe_batch_set_option(swe_batch *bt, int32_t key, int64_t value)
         bt->implicit = value != 0;
         return SWE_OK;
     }
+    if (key == SWE_OPT_LOCAL_SPLIT) {
+        bt->local_split = value != 0;
+        return SWE_OK;
+    }
     if (key != SWE_OPT_COMPENSATED) return SWE_EINVAL;
     for (auto &s : bt->sc) {
         const int rc = batch_residuals(bt, s, value != 0);
@@ -308,7 +314,7 @@ int swe_batch_run(swe_batch *bt, int32_t max_steps)
         ks.push_back(k);
     }
     const int rc = bt->seg.run(geos, ks, batch_variant(bt), bt->mode, bt->use_graph, bt->stream, bt->implicit,
-                               bt->compensated);
+                               bt->compensated, bt->local_split);
     if (rc) return rc;
     for (size_t i = 0; i < bt->sc.size(); ++i) bt->sc[i].done += ks[i];
     return SWE_OK;

@@ -40,7 +40,7 @@ struct BatchTables {
     int nrounds, nact, group;
 };
 
-template <class C, int W, bool IMP, bool CMP>
+template <class C, int W, bool IMP, bool CMP, bool LLF = false>
 __global__ __launch_bounds__(C::NT, W) void k_persistent(BatchTables T)
 {
     __shared__ float lds[C::LDS_FLOATS];
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(C::NT, W) void k_persistent(BatchTables T)
                 while (l >= T.prefix[slot + 1]) ++slot;
                 const int tl = l - T.prefix[slot];
                 const int ntx = T.ntx[slot];
-                stage_tile<C, false, CMP, IMP>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, r % 3 + 1);
+                stage_tile<C, false, CMP, IMP, LLF>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, r % 3 + 1);
                 __syncthreads();
             }
             // every wave makes its own stores visible at agent scope before
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(C::NT, W) void k_persistent(BatchTables T)
     }
 }
 
-template <class C, int S, int W, bool IMP, bool CMP>
+template <class C, int S, int W, bool IMP, bool CMP, bool LLF = false>
 __global__ __launch_bounds__(C::NT, W) void k_round(BatchTables T, int nact_round, int nblocks)
 {
     __shared__ float lds[C::LDS_FLOATS];
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(C::NT, W) void k_round(BatchTables T, int nact_roun
     const int slot = upper_index(T.prefix, nact_round, id);
     const int tl = id - T.prefix[slot];
     const int ntx = T.ntx[slot];
-    stage_tile<C, (W <= 2), CMP, IMP>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, S);
+    stage_tile<C, (W <= 2), CMP, IMP, LLF>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, S);
 }
 
 struct BatchKernels {
@@ -116,16 +116,20 @@ struct BatchKernels {
 };
 
 // Kernels of one tile variant; IMP: point-implicit friction, CMP: the
-// compensated level (every scenario of the run carries residual planes).
-#define SWE_BK_M(TX, TY, R, W, IMP, CMP)                                                         \
-    {k_persistent<TileCfg<TX, TY, R>, W, IMP, CMP>,                                              \
-     {k_round<TileCfg<TX, TY, R>, 1, W, IMP, CMP>, k_round<TileCfg<TX, TY, R>, 2, W, IMP, CMP>,   \
-      k_round<TileCfg<TX, TY, R>, 3, W, IMP, CMP>}},
+// compensated level (every scenario of the run carries residual planes),
+// LLF: local Lax-Friedrichs splitting.
+#define SWE_BK_L(TX, TY, R, W, IMP, CMP, LLF)                                                              \
+    {k_persistent<TileCfg<TX, TY, R>, W, IMP, CMP, LLF>,                                                   \
+     {k_round<TileCfg<TX, TY, R>, 1, W, IMP, CMP, LLF>, k_round<TileCfg<TX, TY, R>, 2, W, IMP, CMP, LLF>, \
+      k_round<TileCfg<TX, TY, R>, 3, W, IMP, CMP, LLF>}},
+#define SWE_BK_M(TX, TY, R, W, IMP, CMP) SWE_BK_L(TX, TY, R, W, IMP, CMP, false)
 #define SWE_BK(TX, TY, R, W, IMP) SWE_BK_M(TX, TY, R, W, IMP, false)
 // In SWE_TILE_LIST order, the same as the single-scenario variant table;
 // one set per translation unit (compiled in parallel): explicit friction in
 // swe_batch.hip, implicit in swe_batch_imp.hip, the compensated level with
-// either in swe_batch_cmp.hip and swe_batch_cmp_imp.hip.
+// either in swe_batch_cmp.hip and swe_batch_cmp_imp.hip, and the same four
+// with local Lax-Friedrichs splitting in swe_batch_llf*.hip.
 extern const BatchKernels g_bk[], g_bk_imp[], g_bk_cmp[], g_bk_cmp_imp[];
+extern const BatchKernels g_bk_llf[], g_bk_llf_imp[], g_bk_llf_cmp[], g_bk_llf_cmp_imp[];
 
 }  // namespace swe

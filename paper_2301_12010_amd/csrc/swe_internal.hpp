@@ -135,9 +135,10 @@ struct SegmentLauncher {
     int group = 0;  // tickets taken per atomic in persistent mode (0: automatic)
     ~SegmentLauncher();
     // implicit: the point-implicit friction kernels; compensated: the
-    // compensated-level kernels (every geo then has residual planes)
+    // compensated-level kernels (every geo then has residual planes);
+    // local_split: the local Lax-Friedrichs kernels
     int run(const std::vector<Geo> &geos, const std::vector<int> &ksteps, int vi, int mode, bool use_graph,
-            hipStream_t stream, bool implicit = false, bool compensated = false);
+            hipStream_t stream, bool implicit = false, bool compensated = false, bool local_split = false);
 };
 
 // Residual planes of the compensated level for one scenario: `mem` holds

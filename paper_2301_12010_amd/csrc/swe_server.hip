@@ -133,6 +133,7 @@ struct swe_server {
     int segment_steps = 100;
     int mode = SWE_BATCH_ROUNDS;
     bool implicit = false;     // point-implicit friction (set before the first submit)
+    bool local_split = false;  // local Lax-Friedrichs splitting (set before the first submit)
     std::atomic<bool> compensated{false};  // compensated level (set before the first submit)
     size_t max_queue = 1 << 16;
     Arena arena;
@@ -218,14 +219,15 @@ void swe_server::loop()
             std::vector<std::pair<int, int>> sizes;
             for (const Geo &g : geos) sizes.emplace_back(g.nx, g.ny);
             int launch_mode;
-            bool launch_implicit;
+            bool launch_implicit, launch_local;
             {
                 std::lock_guard<std::mutex> lk(mu);
                 launch_mode = mode;
                 launch_implicit = implicit;
+                launch_local = local_split;
             }
             rc = seg.run(geos, ks, batch_variant_for(sizes), launch_mode, false, compute, launch_implicit,
-                         compensated);
+                         compensated, launch_local);
             std::lock_guard<std::mutex> lk(mu);
             ++segments;
             if (rc) fatal = rc;
@@ -434,11 +436,13 @@ int swe_server_set_mode(swe_server *sv, int32_t mode)
 
 int swe_server_set_option(swe_server *sv, int32_t key, int64_t value)
 {
-    if (!sv || (key != SWE_OPT_FRICTION_IMPLICIT && key != SWE_OPT_COMPENSATED) || (value != 0 && value != 1))
+    if (!sv || (key != SWE_OPT_FRICTION_IMPLICIT && key != SWE_OPT_COMPENSATED && key != SWE_OPT_LOCAL_SPLIT) ||
+        (value != 0 && value != 1))
         return SWE_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->submitted > 0) return SWE_EBUSY;  // one treatment for every request
     if (key == SWE_OPT_FRICTION_IMPLICIT) sv->implicit = value != 0;
+    else if (key == SWE_OPT_LOCAL_SPLIT) sv->local_split = value != 0;
     else sv->compensated = value != 0;
     return SWE_OK;
 }

@@ -2,8 +2,10 @@
 checker's variant (reading R11), element by element on the same seeded
 inputs; still water stays at rest; every tile variant and the transposed
 problem give the same state bitwise; the 4096^2 coastline in the launch
-configuration the bench times for it."""
+configuration the bench times for it; batches and served requests with the
+option advance bitwise as contexts with it."""
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -135,3 +137,65 @@ def test_large_coast_first_steps_against_checker():
     assert_front_parity(g, r, TOL_SMOOTH, "coast 4096^2, local split, 10 steps")
     assert_epilogue_parity(st, rs, coast, "coast 4096^2, local split")
     assert abs(st["t"] - rs["t"]) <= 1e-6 * rs["t"]
+
+
+def context_run(sc, n, implicit=0):
+    s = swe.Solver.from_scenario(sc)
+    s.set_option(swe.OPT_TILE, 1)
+    s.set_option(swe.OPT_LOCAL_SPLIT, 1)
+    s.set_option(swe.OPT_FRICTION_IMPLICIT, implicit)
+    s.step(n)
+    out = s.read()
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("mode,graph,implicit", [(swe.BATCH_ROUNDS, True, 0), (swe.BATCH_PERSISTENT, False, 0),
+                                                 (swe.BATCH_ROUNDS, False, 1)])
+def test_batch_equals_contexts_bitwise(mode, graph, implicit):
+    mix = [(inputs.random_wet(64, 48, seed=31), 6), (inputs.random_wet(130, 70, seed=32, dry_fraction=0.05), 9),
+           (inputs.dam_break(nx=200, ny=100), 7), (inputs.parabolic_bowl(nx=150, ny=9, dx=4.0), 11),
+           (inputs.random_wet(100, 37, seed=33, dry_fraction=0.1, manning=0.05), 5)]
+    say(f"local split batch mode={mode} graph={graph} implicit={implicit}")
+    bt = swe.Batch()
+    bt.set_mode(mode, graph)
+    bt.set_tile(1)
+    bt.set_option(swe.OPT_LOCAL_SPLIT, 1)
+    bt.set_option(swe.OPT_FRICTION_IMPLICIT, implicit)
+    idx = [bt.add_scenario(sc, n) for sc, n in mix]
+    bt.run()
+    for i, (sc, n) in zip(idx, mix):
+        got = bt.read(i)
+        ref = context_run(sc, n, implicit)
+        assert got[3]["step"] == n
+        for a, b in zip(got[:3], ref[:3]):
+            assert np.array_equal(a, b), (sc.name, n)
+        assert got[3]["t"] == ref[3]["t"]
+    bt.close()
+
+
+def test_served_requests_equal_contexts_bitwise():
+    mix = [(inputs.random_wet(64, 48, seed=34, dry_fraction=0.05), 13), (inputs.dam_break(nx=128, ny=64), 20)]
+    sv = swe.Server(mem_budget=256 << 20, max_slots=8, segment_steps=5)
+    sv.set_option(swe.OPT_LOCAL_SPLIT, 1)
+    tickets = [sv.submit_scenario(sc, n) for sc, n in mix]
+    with pytest.raises(swe.SweError) as ei:
+        sv.set_option(swe.OPT_LOCAL_SPLIT, 0)
+    assert ei.value.code == swe.EBUSY
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets):
+        for tk in tickets:
+            if tk not in done:
+                r, st = sv.poll(tk)
+                if r["status"] != swe.PENDING:
+                    done[tk] = (r, st)
+        assert time.time() - t0 < 60.0, "server did not finish in time"
+        time.sleep(0.002)
+    for tk, (sc, n) in zip(tickets, mix):
+        r, state = done[tk]
+        assert r["status"] == swe.DONE
+        ref = context_run(sc, n)
+        for a, b in zip(state, ref[:3]):
+            assert np.array_equal(a, b), sc.name
+    sv.close()
