@@ -335,7 +335,9 @@ typedef struct swe_result {
 } swe_result;
 
 typedef struct swe_server_stats {
-    int64_t submitted, completed, failed, cancelled, queued, active;
+    int64_t submitted, completed, failed, cancelled;
+    int64_t queued;  /* waiting for admission */
+    int64_t active;  /* admitted: resident, or being uploaded to join the next segment */
     size_t mem_in_use, mem_high_water, mem_budget;
     int64_t segments;  /* segments run so far */
 } swe_server_stats;

@@ -1,16 +1,17 @@
 // swe_server.hip - continuous batching of scenario requests.
 //
-// A host thread owns a device arena of the memory budget.  Requests wait in a
-// FIFO queue; a request is admitted when a slot is free and its footprint
-// (swe_footprint) fits a first-fit hole of the arena, so admission is by HBM
-// footprint and allocates no device memory after create.  Resident scenarios advance
-// together in segments: one launch sequence advances every resident scenario
-// by min(segment_steps, its remaining steps).  While a segment runs, the
-// thread prepares and uploads newly admitted requests on a copy stream and
-// copies the results of scenarios finished in the previous segment back to
-// host memory; those scenarios then leave the arena, and the uploaded ones
-// join at the next segment.  The compute stream therefore never waits for
-// host-side preparation or transfers while resident work remains.  Every scenario
+// The server owns a device arena of the memory budget and two host threads.
+// Requests wait in a FIFO queue.  The upload thread admits the queue's head
+// when a slot is free and its footprint (swe_footprint) fits a first-fit hole
+// of the arena, so admission is by HBM footprint and allocates no device
+// memory after create; it prepares the request's device planes on its own
+// stream and hands the request to the segment thread.  The segment thread
+// advances every resident scenario in segments: one launch sequence advances
+// each by min(segment_steps, its remaining steps); uploaded requests join at
+// the next segment.  While a segment runs, the segment thread copies the
+// results of scenarios finished in the previous segment back to host memory,
+// and those leave the arena.  Neither host-side preparation nor transfers
+// hold up the compute stream while resident work remains.  Every scenario
 // runs the same per-tile stage code as alone, so its result does not depend
 // on what else is in the mix.
 #include <hip/hip_runtime.h>
@@ -137,21 +138,26 @@ struct swe_server {
     std::atomic<bool> compensated{false};  // compensated level (set before the first submit)
     size_t max_queue = 1 << 16;
     Arena arena;
-    hipStream_t compute = nullptr, copy = nullptr;
+    hipStream_t compute = nullptr, copy = nullptr, upload = nullptr;
     SegmentLauncher seg;
-    std::thread th;
+    std::thread th, up;  // segment thread, upload thread
     std::mutex mu;
-    std::condition_variable cv;
+    std::condition_variable cv;     // segment thread: requests ready, cancel, stop
+    std::condition_variable cv_up;  // upload thread: submit, memory released, cancel, stop
     bool stop = false;
     uint64_t next_ticket = 1;
     std::deque<Request *> queue;
-    std::vector<Request *> active;
+    std::vector<Request *> ready;   // uploaded, joining at the next segment
+    std::vector<Request *> active;  // resident in the segment thread
+    int uploading = 0;              // admitted, upload in progress
     std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
     int64_t submitted = 0, completed = 0, failed = 0, cancelled = 0, segments = 0;
     int fatal = SWE_OK;
 
     void loop();
-    int admit_locked(std::vector<Request *> &admitted);
+    void uploader();
+    Request *admit_one_locked();
+    void release_locked(Request *r);
     void finish(Request *r, int status, int error);
 };
 
@@ -165,10 +171,12 @@ void swe_server::finish(Request *r, int status, int error)
     else ++failed;
 }
 
-// Moves queued requests that fit into the arena; caller holds `mu`.
-int swe_server::admit_locked(std::vector<Request *> &admitted)
+// Admits the queue's head if a slot is free and its footprint fits a hole of
+// the arena (first in, first out: a head that does not fit waits for memory);
+// cancelled heads end here.  Caller holds `mu`.
+Request *swe_server::admit_one_locked()
 {
-    while (!queue.empty() && (int)(active.size() + admitted.size()) < max_slots) {
+    while (!queue.empty() && (int)(active.size() + ready.size()) + uploading < max_slots) {
         Request *r = queue.front();
         if (r->cancel) {
             queue.pop_front();
@@ -177,13 +185,63 @@ int swe_server::admit_locked(std::vector<Request *> &admitted)
             continue;
         }
         void *mem = arena.alloc(request_bytes(r->p, r->track_max, compensated));
-        if (!mem) break;  // FIFO: wait for memory to free up
+        if (!mem) return nullptr;
         queue.pop_front();
         r->d.base = mem;
         r->t_admit = now_seconds();
-        admitted.push_back(r);
+        ++uploading;
+        return r;
     }
-    return SWE_OK;
+    return nullptr;
+}
+
+// Returns a request's device memory to the arena; caller holds `mu`.
+void swe_server::release_locked(Request *r)
+{
+    arena.release(r->d.base, request_bytes(r->p, r->track_max, compensated));
+    r->d.base = nullptr;
+    cv_up.notify_one();
+}
+
+void swe_server::uploader()
+{
+    (void)hipSetDevice(device);
+    for (;;) {
+        Request *r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            for (;;) {
+                if (stop) return;
+                if ((r = admit_one_locked())) break;
+                cv_up.wait(lk);
+            }
+        }
+        int urc = scenario_upload_into(r->d.base, r->p, r->f, upload, r->d);
+        if (!urc && r->track_max) {
+            // the map's plane follows the scenario; it starts at the depth
+            r->d.geo.hmax =
+                reinterpret_cast<float *>(static_cast<char *>(r->d.base) + scenario_bytes(r->p.nx, r->p.ny));
+            urc = launch_depth(r->d.geo, r->d.geo.U[0], r->d.geo.hmax, upload);
+        }
+        if (!urc && compensated) {
+            // the residual planes come last
+            char *rp = static_cast<char *>(r->d.base) + scenario_bytes(r->p.nx, r->p.ny) +
+                       (r->track_max ? map_bytes(r->p) : 0);
+            urc = attach_residuals(r->d.geo, reinterpret_cast<float *>(rp), upload);
+        }
+        // the segment thread uses the planes only after this wait
+        if (!urc && hipStreamSynchronize(upload) != hipSuccess) urc = SWE_EDEVICE;
+        std::lock_guard<std::mutex> lk(mu);
+        --uploading;
+        r->f = HostFields();
+        if (urc) {
+            release_locked(r);
+            finish(r, SWE_FAILED, urc);
+        } else {
+            ready.push_back(r);
+            cv.notify_one();
+        }
+    }
 }
 
 void swe_server::loop()
@@ -191,12 +249,12 @@ void swe_server::loop()
     (void)hipSetDevice(device);
     std::vector<Request *> retiring;  // finished in the previous segment, results not yet copied
     for (;;) {
-        std::vector<Request *> admitted;
         {
             std::unique_lock<std::mutex> lk(mu);
             if (stop) break;
-            admit_locked(admitted);
-            if (active.empty() && admitted.empty() && retiring.empty()) {
+            active.insert(active.end(), ready.begin(), ready.end());
+            ready.clear();
+            if (active.empty() && retiring.empty()) {
                 cv.wait_for(lk, std::chrono::milliseconds(20));
                 continue;
             }
@@ -232,34 +290,8 @@ void swe_server::loop()
             ++segments;
             if (rc) fatal = rc;
         }
-        // while the segment runs: upload the admitted requests (copy stream;
-        // they join at the next segment) ...
-        std::vector<Request *> joining;
-        for (Request *r : admitted) {
-            int urc = scenario_upload_into(r->d.base, r->p, r->f, copy, r->d);
-            if (!urc && r->track_max) {
-                // the map's plane follows the scenario; it starts at the depth
-                r->d.geo.hmax = reinterpret_cast<float *>(static_cast<char *>(r->d.base) +
-                                                          scenario_bytes(r->p.nx, r->p.ny));
-                urc = launch_depth(r->d.geo, r->d.geo.U[0], r->d.geo.hmax, copy);
-            }
-            if (!urc && compensated) {
-                // the residual planes come last
-                char *rp = static_cast<char *>(r->d.base) + scenario_bytes(r->p.nx, r->p.ny) +
-                           (r->track_max ? map_bytes(r->p) : 0);
-                urc = attach_residuals(r->d.geo, reinterpret_cast<float *>(rp), copy);
-            }
-            std::lock_guard<std::mutex> lk(mu);
-            r->f = HostFields();
-            if (urc) {
-                arena.release(r->d.base, request_bytes(r->p, r->track_max, compensated));
-                r->d.base = nullptr;
-                finish(r, SWE_FAILED, urc);
-            } else {
-                joining.push_back(r);
-            }
-        }
-        // ... and copy out the results of the previous segment's finishers
+        // while the segment runs: copy out the results of the previous
+        // segment's finishers
         for (Request *r : retiring) {
             int rrc = SWE_OK;
             if (!r->cancel) {
@@ -280,8 +312,7 @@ void swe_server::loop()
                 if (!rrc) rrc = src;
             }
             std::lock_guard<std::mutex> lk(mu);
-            arena.release(r->d.base, request_bytes(r->p, r->track_max, compensated));
-            r->d.base = nullptr;
+            release_locked(r);
             if (r->cancel) finish(r, SWE_CANCELLED, SWE_OK);
             else if (rrc == SWE_OK) finish(r, SWE_DONE, SWE_OK);
             else finish(r, SWE_FAILED, rrc);
@@ -308,8 +339,7 @@ void swe_server::loop()
                 }
             if (out) {
                 if (r->error != SWE_OK && !r->cancel) {
-                    arena.release(r->d.base, request_bytes(r->p, r->track_max, compensated));
-                    r->d.base = nullptr;
+                    release_locked(r);
                     finish(r, SWE_FAILED, r->error);
                 } else {
                     retiring.push_back(r);
@@ -318,7 +348,6 @@ void swe_server::loop()
                 keep.push_back(r);
             }
         }
-        keep.insert(keep.end(), joining.begin(), joining.end());
         active.swap(keep);
     }
     // shutdown: drop whatever is resident
@@ -352,12 +381,15 @@ int swe_server_create(int32_t device, size_t mem_budget, int32_t max_slots, int3
         return rc;
     }
     if (hipStreamCreateWithFlags(&sv->compute, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&sv->copy, hipStreamNonBlocking) != hipSuccess) {
+        hipStreamCreateWithFlags(&sv->copy, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&sv->upload, hipStreamNonBlocking) != hipSuccess) {
         if (sv->compute) (void)hipStreamDestroy(sv->compute);
+        if (sv->copy) (void)hipStreamDestroy(sv->copy);
         delete sv;
         return SWE_EDEVICE;
     }
     sv->th = std::thread([sv] { sv->loop(); });
+    sv->up = std::thread([sv] { sv->uploader(); });
     *out = sv;
     return SWE_OK;
 }
@@ -381,7 +413,7 @@ int swe_submit_ex(swe_server *sv, const swe_params *p, const float *b, const flo
     sv->queue.push_back(r.get());
     sv->reqs[r->ticket] = std::move(r);
     ++sv->submitted;
-    sv->cv.notify_one();
+    sv->cv_up.notify_one();
     return SWE_OK;
 }
 
@@ -455,6 +487,7 @@ int swe_cancel(swe_server *sv, uint64_t ticket)
     if (it == sv->reqs.end()) return SWE_ENOTFOUND;
     it->second->cancel = true;
     sv->cv.notify_one();
+    sv->cv_up.notify_one();
     return SWE_OK;
 }
 
@@ -467,7 +500,7 @@ int swe_server_get_stats(swe_server *sv, swe_server_stats *st)
     st->failed = sv->failed;
     st->cancelled = sv->cancelled;
     st->queued = (int64_t)sv->queue.size();
-    st->active = (int64_t)sv->active.size();
+    st->active = (int64_t)(sv->active.size() + sv->ready.size()) + sv->uploading;
     st->mem_in_use = sv->arena.used();
     st->mem_high_water = sv->arena.high_water();
     st->mem_budget = sv->arena.capacity();
@@ -483,9 +516,12 @@ void swe_server_destroy(swe_server *sv)
         sv->stop = true;
     }
     sv->cv.notify_all();
+    sv->cv_up.notify_all();
+    if (sv->up.joinable()) sv->up.join();
     if (sv->th.joinable()) sv->th.join();
     (void)hipStreamDestroy(sv->compute);
     (void)hipStreamDestroy(sv->copy);
+    (void)hipStreamDestroy(sv->upload);
     delete sv;
 }
 
