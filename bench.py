@@ -624,9 +624,10 @@ def main():
     ap.add_argument("--serve-budget-gb", type=int, default=2)
     ap.add_argument("--serve-slots", type=int, default=64,
                     help="requests resident and stepped together (the server's max_slots)")
-    ap.add_argument("--workload", choices=("coast", "uneven", "serving"), default="coast",
+    ap.add_argument("--workload", choices=("coast", "uneven", "serving", "serving-ensemble"), default="coast",
                     help="coast: every line (default); uneven: the 200-scenario uneven batch alone; "
-                         "serving: the uneven batch, then Poisson serving at --serve-loads of its capacity")
+                         "serving: the uneven batch, then Poisson serving at --serve-loads of its capacity; "
+                         "serving-ensemble: the same on the ensemble's all-1024^2 mix")
     ap.add_argument("--uneven-count", type=int, default=200)
     ap.add_argument("--uneven-tile", type=int, default=-1,
                     help="tile variant of the uneven batch's launches (-1: the one tuned for its largest size)")
@@ -656,6 +657,27 @@ def main():
     from paper_2301_12010_amd import inputs, swe
 
     torch.cuda.set_device(0)
+    if args.workload == "serving-ensemble":
+        # the same serving measurement on the ensemble's mix: every request a
+        # 1024^2 N-wave member (request i = member i mod count) of ens_steps
+        # steps, at the loads of the ensemble's batched capacity
+        args.ens_modes = ["rounds_graph"]
+        batched, members = run_batched(args, torch, inputs, swe)
+        cap = batched["scenarios_per_hour"] / 3600.0
+        n = args.serve_requests
+        out = {"batched": batched,
+               "serving": {"workload": f"poisson_requests_ensemble_mix_{n}", "capacity_scenarios_per_s": cap,
+                           "mix": "the ensemble members, %d steps each" % args.ens_steps}}
+        for frac in args.serve_loads:
+            res = run_serving(swe, members, [args.ens_steps] * n, frac * cap, args.serve_budget_gb << 30,
+                              args.serve_slots, label=f"{frac}x")
+            res["load_fraction"] = frac
+            out["serving"][f"load_{frac}"] = res
+            log(f"serving (ensemble mix) at {frac}x capacity: p50 {res['p50_time_to_result_s']:.2f}s "
+                f"p99 {res['p99_time_to_result_s']:.2f}s, {res['scenarios_per_hour']:.0f} scenarios/hour, "
+                f"high water {res['mem_high_water_bytes'] / 1e9:.2f} GB")
+        print(json.dumps(out), flush=True)
+        return
     if args.workload in ("uneven", "serving"):
         res, scens, plan = run_uneven(args, torch, inputs, swe)
         out = {"uneven": res}
