@@ -345,7 +345,10 @@ typedef struct swe_server_stats {
 /* Start a server on `device` with a device-memory budget for scenario state
  * (bytes; 0 = half of the device's free memory), at most max_slots resident
  * scenarios, and segment_steps steps per segment (one batched run of every
- * resident request) between admissions. */
+ * resident request) between admissions.  The server runs segments, uploads
+ * and read-backs on three streams of its own; a process that also uses other
+ * streams should allow HIP enough hardware queues (GPU_MAX_HW_QUEUES, 8 or
+ * more) to keep them on separate queues, or uploads wait behind segments. */
 int swe_server_create(int32_t device, size_t mem_budget, int32_t max_slots,
                       int32_t segment_steps, swe_server **out);
 

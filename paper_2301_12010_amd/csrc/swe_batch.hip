@@ -56,6 +56,7 @@ SegmentLauncher::~SegmentLauncher()
 {
     if (graph) (void)hipGraphExecDestroy(graph);
     dev_free(dmem);
+    if (hbuf) (void)hipHostFree(hbuf);
 }
 
 int SegmentLauncher::run(const std::vector<Geo> &geos, const std::vector<int> &ksteps, int vi, int mode,
@@ -104,8 +105,17 @@ int SegmentLauncher::run(const std::vector<Geo> &geos, const std::vector<int> &k
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (cus <= 0) cus = 256;
     }
-    hbuf.assign(o_done, 0);
-    char *hb = hbuf.data();
+    if (o_done > hbytes) {
+        // pinned, so that the upload below is asynchronous; reused while
+        // large enough (the previous run's copy is complete: see above)
+        if (hbuf) (void)hipHostFree(hbuf);
+        hbuf = nullptr;
+        hbytes = 0;
+        SWE_HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&hbuf), o_done * 2, hipHostMallocDefault));
+        hbytes = o_done * 2;
+    }
+    char *hb = hbuf;
+    std::memset(hb, 0, o_done);
     std::memcpy(hb + o_geo, geos.data(), n * sizeof(Geo));
     std::memcpy(hb + o_order, order.data(), nact * sizeof(int));
     std::memcpy(hb + o_prefix, prefix.data(), (nact + 1) * sizeof(int));

@@ -129,7 +129,8 @@ double now_seconds();
 struct SegmentLauncher {
     void *dmem = nullptr;
     size_t dbytes = 0;
-    std::vector<char> hbuf;
+    char *hbuf = nullptr;  // pinned host copy of the tables (asynchronous upload)
+    size_t hbytes = 0;
     hipGraphExec_t graph = nullptr;
     int cus = 0;
     int group = 0;  // tickets taken per atomic in persistent mode (0: automatic)

@@ -139,6 +139,7 @@ struct swe_server {
     size_t max_queue = 1 << 16;
     Arena arena;
     hipStream_t compute = nullptr, copy = nullptr, upload = nullptr;
+    DevScen *ds_host = nullptr;  // pinned: the resident scenarios' scalars after a segment
     SegmentLauncher seg;
     std::thread th, up;  // segment thread, upload thread
     std::mutex mu;
@@ -320,7 +321,7 @@ void swe_server::loop()
         retiring.clear();
         if (hipStreamSynchronize(compute) != hipSuccess) rc = SWE_EDEVICE;
         // account the segment, detect failures, pick the finishers
-        std::vector<DevScen> ds(in_seg.size());
+        DevScen *ds = ds_host;
         for (size_t i = 0; i < in_seg.size(); ++i)
             (void)hipMemcpyAsync(&ds[i], in_seg[i]->d.geo.sd, sizeof(DevScen), hipMemcpyDeviceToHost, copy);
         (void)hipStreamSynchronize(copy);
@@ -387,6 +388,14 @@ int swe_server_create(int32_t device, size_t mem_budget, int32_t max_slots, int3
         if (sv->copy) (void)hipStreamDestroy(sv->copy);
         delete sv;
         return SWE_EDEVICE;
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&sv->ds_host), (size_t)max_slots * sizeof(DevScen),
+                      hipHostMallocDefault) != hipSuccess) {
+        (void)hipStreamDestroy(sv->compute);
+        (void)hipStreamDestroy(sv->copy);
+        (void)hipStreamDestroy(sv->upload);
+        delete sv;
+        return SWE_ENOMEM;
     }
     sv->th = std::thread([sv] { sv->loop(); });
     sv->up = std::thread([sv] { sv->uploader(); });
@@ -522,6 +531,7 @@ void swe_server_destroy(swe_server *sv)
     (void)hipStreamDestroy(sv->compute);
     (void)hipStreamDestroy(sv->copy);
     (void)hipStreamDestroy(sv->upload);
+    (void)hipHostFree(sv->ds_host);
     delete sv;
 }
 
