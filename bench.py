@@ -45,8 +45,14 @@ sys.path.insert(0, ROOT)
 # at most GPU_MAX_HW_QUEUES hardware queues (4 by default); after the earlier
 # lines' contexts and batches, the server's streams shared queues and its
 # uploads serialized with the segments (serving p50 at 0.7x load 1.44 s
-# against 0.90 s with 8 queues, same run otherwise).  Set before HIP starts.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# against 0.90 s with 8 queues, same run otherwise).  Raised (never lowered)
+# before HIP starts.
+try:
+    _hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+except ValueError:
+    _hwq = 4
+if _hwq < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 METRIC = "cell-RK3-updates/s FP32 (1 GPU); scenarios/hour + p50/p99 latency batched"
 UNIT = "cell-RK3-updates/s"
