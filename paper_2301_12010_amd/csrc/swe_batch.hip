@@ -83,7 +83,9 @@ int SegmentLauncher::run(const std::vector<Geo> &geos, const std::vector<int> &k
     const size_t o_ntx = o_prefix + al((nact + 1) * sizeof(int));
     const size_t o_rstart = o_ntx + al(nact * sizeof(int));
     const size_t o_ract = o_rstart + al((nrounds + 1) * sizeof(long long));
-    const size_t o_done = o_ract + al(nrounds * sizeof(int));
+    const size_t o_blk = o_ract + al(nrounds * sizeof(int));
+    const int ntiles = prefix[nact];
+    const size_t o_done = o_blk + al((size_t)ntiles * sizeof(int2));
     const size_t o_ticket = o_done + al(nact * sizeof(unsigned int));
     const size_t need = o_ticket + al(sizeof(unsigned long long));
     SWE_HIP_TRY(hipStreamSynchronize(stream));  // the previous segment's tables are free
@@ -122,6 +124,9 @@ int SegmentLauncher::run(const std::vector<Geo> &geos, const std::vector<int> &k
     std::memcpy(hb + o_ntx, ntx.data(), nact * sizeof(int));
     std::memcpy(hb + o_rstart, rstart.data(), (nrounds + 1) * sizeof(long long));
     std::memcpy(hb + o_ract, ractive.data(), nrounds * sizeof(int));
+    int2 *blk = reinterpret_cast<int2 *>(hb + o_blk);
+    for (int q = 0; q < nact; ++q)
+        for (int l = prefix[q]; l < prefix[q + 1]; ++l) blk[l] = make_int2(order[q], l - prefix[q]);
     SWE_HIP_TRY(hipMemcpyAsync(dmem, hb, o_done, hipMemcpyHostToDevice, stream));
 
     char *dm = static_cast<char *>(dmem);
@@ -132,6 +137,7 @@ int SegmentLauncher::run(const std::vector<Geo> &geos, const std::vector<int> &k
     T.ntx = reinterpret_cast<const int *>(dm + o_ntx);
     T.rstart = reinterpret_cast<const long long *>(dm + o_rstart);
     T.ractive = reinterpret_cast<const int *>(dm + o_ract);
+    T.blk = reinterpret_cast<const int2 *>(dm + o_blk);
     T.done = reinterpret_cast<unsigned int *>(dm + o_done);
     T.ticket = reinterpret_cast<unsigned long long *>(dm + o_ticket);
     T.nrounds = nrounds;

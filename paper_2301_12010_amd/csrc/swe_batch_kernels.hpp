@@ -30,6 +30,7 @@ __device__ __forceinline__ int upper_index(const T *a, int n, T v)
 
 struct BatchTables {
     const Geo *geo;            // per scenario (batch order)
+    const int2 *blk;           // per tile of round 0: (scenario index, tile of that scenario)
     const int *order;          // sorted position -> scenario
     const int *prefix;         // tile prefix over sorted positions (size nact + 1)
     const int *ntx;            // tiles along x per sorted position
@@ -103,11 +104,15 @@ template <class C, int S, int W, bool IMP, bool CMP, bool LLF = false>
 __global__ __launch_bounds__(C::NT, W) void k_round(BatchTables T, int nact_round, int nblocks)
 {
     __shared__ float lds[C::LDS_FLOATS];
+    // the round's tiles are the first nblocks of round 0's (its scenarios are
+    // a prefix of the sorted order): one table load names the block's
+    // scenario and tile, with no search over the prefix sums
+    (void)nact_round;
     const int id = xcd_remap_b(blockIdx.x, nblocks);
-    const int slot = upper_index(T.prefix, nact_round, id);
-    const int tl = id - T.prefix[slot];
-    const int ntx = T.ntx[slot];
-    stage_tile<C, (W <= 2), CMP, IMP, LLF>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, S);
+    const int2 e = T.blk[id];
+    const Geo &G = T.geo[e.x];
+    const int ntx = (G.nx + C::TX - 1) / C::TX;
+    stage_tile<C, (W <= 2), CMP, IMP, LLF>(G, e.y % ntx, e.y / ntx, lds, S);
 }
 
 struct BatchKernels {
