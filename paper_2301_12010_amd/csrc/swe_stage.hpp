@@ -565,15 +565,13 @@ struct StagePartials {
 
 template <class C>
 struct TileRegs {
-    static constexpr int NE = C::WX * C::WY;
-    static constexpr int IT_ANY = (NE + C::NT - 1) / C::NT;  // element rounds (edge tiles)
-    // interior tiles: passes over the first TX staged columns, RPI rows per
-    // pass (thread = (row q, column c)), then the 2 HALO last columns
+    // passes over the first TX staged columns, RPI rows per pass (thread =
+    // (row q, column c)), then the 2 HALO last columns
     static constexpr int RPI = C::NT / C::TX;
     static constexpr int MI = (C::WY + RPI - 1) / RPI;
     static constexpr int NR = 2 * HALO * C::WY;
     static constexpr int RI = (NR + C::NT - 1) / C::NT;
-    static constexpr int IT = IT_ANY > MI + RI ? IT_ANY : MI + RI;
+    static constexpr int IT = MI + RI;
     static_assert(C::NT % C::TX == 0, "whole rows of threads per pass");
     float h[IT], hu[IT], hv[IT], b[IT];
 };
@@ -585,6 +583,14 @@ __device__ __forceinline__ bool tile_inner(const Geo &G, int tx, int ty)
 {
     const int x0 = tx * C::TX, y0 = ty * C::TY;
     return x0 >= HALO && y0 >= HALO && x0 + C::TX + HALO <= G.nx && y0 + C::TY + HALO <= G.ny;
+}
+
+// Grid index of staged coordinate g along a side of n cells: ghosts of a
+// mirrored side read the mirror cell; clamped into the grid.
+__device__ __forceinline__ int mirror_index(int g, int n)
+{
+    int m = g < 0 ? -1 - g : (g >= n ? 2 * n - 1 - g : g);
+    return m < 0 ? 0 : (m >= n ? n - 1 : m);
 }
 
 // Global loads of a tile and its halo.  Ghost cells of mirrored sides read
@@ -599,12 +605,12 @@ __device__ __forceinline__ void tile_load(const Geo &G, int STAGE, int tx, int t
     const int nx = G.nx, ny = G.ny, pitch = G.pitch;
     const int x0 = tx * C::TX, y0 = ty * C::TY;
     using T = TileRegs<C>;
+    const int c = threadIdx.x % C::TX, q = threadIdx.x / C::TX;
     if (INNER) {
         // every pass whose rows lie in the window reads at one per-thread
         // offset from plane bases advanced by the pass's rows (uniform), so
         // the loads need no per-load vector arithmetic; rows of a last,
         // partial pass are clamped to the window's last row
-        const int c = threadIdx.x % C::TX, q = threadIdx.x / C::TX;
         const unsigned off = (unsigned)((y0 - HALO + q) * pitch + x0 - HALO + c);
 #pragma unroll
         for (int k = 0; k < T::MI; ++k) {
@@ -636,25 +642,31 @@ __device__ __forceinline__ void tile_load(const Geo &G, int STAGE, int tx, int t
         }
         return;
     }
-    constexpr int NE = T::NE, IT = T::IT_ANY;
+    // edge tiles: the same passes.  Ghost cells of mirrored sides read the
+    // mirror cell and indices are clamped into the grid, so the cells beyond
+    // three ghost layers that only ragged tail tiles touch read finite values
+    // whose results are discarded.  A thread's column, and so its mirrored
+    // column, is the same in every pass.
+    const int mx = mirror_index(x0 - HALO + c, nx);
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        // spare threads of the last round restage the tile's last cell
-        // (same value to the same LDS word), which keeps the round branch-free
-        int e = threadIdx.x + it * C::NT;
-        e = (IT * C::NT == NE || e < NE) ? e : NE - 1;
-        const int r = e / C::WX;
-        const int cc = e - r * C::WX;
-        const int gx = x0 - HALO + cc, gy = y0 - HALO + r;
-        int mx = gx < 0 ? -1 - gx : (gx >= nx ? 2 * nx - 1 - gx : gx);
-        int my = gy < 0 ? -1 - gy : (gy >= ny ? 2 * ny - 1 - gy : gy);
-        mx = mx < 0 ? 0 : (mx >= nx ? nx - 1 : mx);
-        my = my < 0 ? 0 : (my >= ny ? ny - 1 : my);
-        const unsigned i = (unsigned)(my * pitch + mx);
-        v.h[it] = pld(w0, i);
-        v.hu[it] = pld(w1, i);
-        v.hv[it] = pld(w2, i);
-        v.b[it] = pld(G.b, i);
+    for (int k = 0; k < T::MI; ++k) {
+        const int r = q + k * T::RPI < C::WY ? q + k * T::RPI : C::WY - 1;
+        const unsigned i = (unsigned)(mirror_index(y0 - HALO + r, ny) * pitch + mx);
+        v.h[k] = pld(w0, i);
+        v.hu[k] = pld(w1, i);
+        v.hv[k] = pld(w2, i);
+        v.b[k] = pld(G.b, i);
+    }
+#pragma unroll
+    for (int j = 0; j < T::RI; ++j) {
+        int e = threadIdx.x + j * C::NT;
+        e = (T::RI * C::NT == T::NR || e < T::NR) ? e : T::NR - 1;
+        const int r = e / (2 * HALO), cc = C::TX + e % (2 * HALO);
+        const unsigned i = (unsigned)(mirror_index(y0 - HALO + r, ny) * pitch + mirror_index(x0 - HALO + cc, nx));
+        v.h[T::MI + j] = pld(w0, i);
+        v.hu[T::MI + j] = pld(w1, i);
+        v.hv[T::MI + j] = pld(w2, i);
+        v.b[T::MI + j] = pld(G.b, i);
     }
 }
 
@@ -667,9 +679,9 @@ __device__ __forceinline__ void tile_store(const Geo &G, int tx, int ty, const T
     const int nx = G.nx, ny = G.ny;
     const int x0 = tx * C::TX, y0 = ty * C::TY;
     using T = TileRegs<C>;
+    const int c = threadIdx.x % C::TX, q = threadIdx.x / C::TX;
     if (INNER) {
         // the pass layout of tile_load: one LDS index plus a constant per pass
-        const int c = threadIdx.x % C::TX, q = threadIdx.x / C::TX;
 #pragma unroll
         for (int k = 0; k < T::MI; ++k) {
             const int r = (k + 1) * T::RPI <= C::WY || q + k * T::RPI < C::WY ? q + k * T::RPI : C::WY - 1;
@@ -691,20 +703,17 @@ __device__ __forceinline__ void tile_store(const Geo &G, int tx, int ty, const T
         }
         return;
     }
-    constexpr int NE = T::NE, IT = T::IT_ANY;
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        int e = threadIdx.x + it * C::NT;
-        e = (IT * C::NT == NE || e < NE) ? e : NE - 1;
-        const int r = e / C::WX;
-        const int cc = e - r * C::WX;
-        const int li = r * C::SX + cc;
+    // edge tiles: the same passes; a FIXED side's frozen values are looked
+    // up only when the tile reaches into that side's ghosts (decided once
+    // for the tile)
+    const bool fixed_near = (x0 < HALO && G.bc[0] == BC_FIXED) || (x0 + C::TX + HALO > nx && G.bc[1] == BC_FIXED) ||
+                            (y0 < HALO && G.bc[2] == BC_FIXED) || (y0 + C::TY + HALO > ny && G.bc[3] == BC_FIXED);
+    auto put = [&](int r, int cc, float h, float hu, float hv, float b) {
         const int gx = x0 - HALO + cc, gy = y0 - HALO + r;
         const bool inx = (unsigned)gx < (unsigned)nx, iny = (unsigned)gy < (unsigned)ny;
-        float h = v.h[it], hu = v.hu[it], hv = v.hv[it], b = v.b[it];
         if (!inx) hu = -hu;
         if (!iny) hv = -hv;
-        if (inx != iny) {
+        if (fixed_near && inx != iny) {
             // a ghost of exactly one side: frozen values if that side is FIXED
             const int side = !inx ? (gx < 0 ? 0 : 1) : (gy < 0 ? 2 : 3);
             const int layer = !inx ? (gx < 0 ? -1 - gx : gx - nx) : (gy < 0 ? -1 - gy : gy - ny);
@@ -716,10 +725,23 @@ __device__ __forceinline__ void tile_store(const Geo &G, int tx, int ty, const T
                 b = G.ghost[ghost_index(G, side, 3, layer, pos)];
             }
         }
+        const int li = r * C::SX + cc;
         Lh[li] = h;
         Lhu[li] = hu;
         Lhv[li] = hv;
         Lb[li] = b;
+    };
+#pragma unroll
+    for (int k = 0; k < T::MI; ++k) {
+        const int r = q + k * T::RPI < C::WY ? q + k * T::RPI : C::WY - 1;
+        put(r, c, v.h[k], v.hu[k], v.hv[k], v.b[k]);
+    }
+#pragma unroll
+    for (int j = 0; j < T::RI; ++j) {
+        int e = threadIdx.x + j * C::NT;
+        e = (T::RI * C::NT == T::NR || e < T::NR) ? e : T::NR - 1;
+        put(e / (2 * HALO), C::TX + e % (2 * HALO), v.h[T::MI + j], v.hu[T::MI + j], v.hv[T::MI + j],
+            v.b[T::MI + j]);
     }
 }
 
