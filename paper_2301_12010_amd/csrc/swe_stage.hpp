@@ -7,10 +7,10 @@
 // Manning sources of Eqs. (2)-(3), with the bed taken relative to the datum.
 //
 // Work layout, per block:
-//   1. the tile's input state (s, hu, hv, b) with a 3-cell cross-shaped halo
-//      is staged in LDS with coalesced row loads (s is the stored level, see
-//      Geo); ghosts are mirrored or read from frozen planes on the fly, so no
-//      separate ghost pass exists;
+//   1. the tile's input state (s, hu, hv, b) with a 3-cell halo is staged in
+//      LDS in coalesced row passes (s is the stored level, see Geo); ghosts
+//      are mirrored or read from frozen planes on the fly, so no separate
+//      ghost pass exists;
 //   2. x sweep: each thread walks R consecutive cells of one row, keeping a
 //      3-cell window of split fluxes in registers.  Every cell centre's
 //      second and first differences, the three smoothness indicators and the
@@ -22,9 +22,8 @@
 //      follow (no per-cell results wait in registers), then the epilogue
 //      reductions (wave shuffles -> LDS -> at most one atomic per block and
 //      quantity) of the next stage's wave speeds, the clamped mass and the
-//      runup.  The FP64
-//      mass is not on the step path: a separate deterministic reduction
-//      computes it when the state is read.
+//      runup.  The FP64 mass is not on the step path: a separate
+//      deterministic reduction computes it when the state is read.
 // The arithmetic of a cell does not depend on the tile shape or on which
 // launch runs the tile, so every tile variant and launch mode gives bitwise
 // identical states.
