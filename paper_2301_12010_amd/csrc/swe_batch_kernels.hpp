@@ -79,7 +79,7 @@ __global__ __launch_bounds__(C::NT, W) void k_persistent(BatchTables T)
                 while (l >= T.prefix[slot + 1]) ++slot;
                 const int tl = l - T.prefix[slot];
                 const int ntx = T.ntx[slot];
-                stage_tile<C, false, CMP, IMP, LLF>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, r % 3 + 1);
+                stage_tile<C, (W <= 2), CMP, IMP, LLF>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, r % 3 + 1);
                 __syncthreads();
             }
             // every wave makes its own stores visible at agent scope before

@@ -746,8 +746,9 @@ __device__ __forceinline__ void tile_store(const Geo &G, int tx, int ty, const T
 
 // Sweeps, sources, RK combination and store of a tile staged in LDS.  Ends
 // with the LDS tile still in use: the caller synchronises before overwriting
-// it.  PF: issue the combination's global reads before the y sweep (costs
-// 4R registers across it; off for variants whose register budget is tight).
+// it.  PF: issue the combination's global reads before the x sweep (costs
+// 4R registers across both sweeps; off for variants whose register budget is
+// tight, those launched for three waves per SIMD).
 // IMP: point-implicit friction.  Each stage takes its own friction term
 // backward in time with the rate kappa of its input, uncapped:
 // q_out = [a_n q^n + a_w (q + dt L')] / (1 + a_w dt kappa), L' without
@@ -773,31 +774,13 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
     K.e1 = G.eps16 * KD1;
     K.e2 = G.eps16 * KD2;
 
-    // ---- x sweep: thread -> (row, segment of R cells) ------------------------
-    {
-        const int row = tid % TY, seg = tid / TY;
-        K.a = sc.ax;
-        K.hinv_ds = 0.5f * G.inv_dx;
-        K.ghinv_ds = -G.g * K.hinv_ds;
-        float *xo = Xr + row * C::XR + seg * R;
-        auto xput = [&](int k, float l0, float l1, float l2) {
-            xo[k] = l0;
-            xo[C::XPLANE + k] = l1;
-            xo[2 * C::XPLANE + k] = l2;
-        };
-        if constexpr (LLF)
-            sweep_llf<R, 0>(Ls, Lhu, Lhv, Lb, (row + HALO) * C::SX + seg * R, 1, K, xput);
-        else
-            sweep<R, 0>(Ls, Lhu, Lhv, Lb, (row + HALO) * C::SX + seg * R, 1, K, xput);
-    }
-    __syncthreads();
-
-    // ---- y sweep, sources, RK combination, store ------------------------------
+    // y-sweep thread -> (column, segment of R cells)
     const int col = tid % TX, seg = tid / TX;
     const int gx = x0 + col;
-    // the per-cell global reads of the combination (g n^2, and u^n in stages
-    // 2 and 3) are issued before the y sweep, so their latency hides behind
-    // it; indices are clamped into the grid (cells outside it are skipped)
+    // the per-cell global reads of the combination in the y sweep (g n^2, and
+    // u^n in stages 2 and 3) are issued before the x sweep, so their HBM
+    // latency hides behind both sweeps; indices are clamped into the grid
+    // (cells outside it are skipped)
     float pgn2[R], pun[R][3];
     if (PF) {
         const int cx = gx < nx ? gx : nx - 1;
@@ -813,6 +796,27 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
             }
         }
     }
+
+    // ---- x sweep: thread -> (row, segment of R cells) ------------------------
+    {
+        const int row = tid % TY, xseg = tid / TY;
+        K.a = sc.ax;
+        K.hinv_ds = 0.5f * G.inv_dx;
+        K.ghinv_ds = -G.g * K.hinv_ds;
+        float *xo = Xr + row * C::XR + xseg * R;
+        auto xput = [&](int k, float l0, float l1, float l2) {
+            xo[k] = l0;
+            xo[C::XPLANE + k] = l1;
+            xo[2 * C::XPLANE + k] = l2;
+        };
+        if constexpr (LLF)
+            sweep_llf<R, 0>(Ls, Lhu, Lhv, Lb, (row + HALO) * C::SX + xseg * R, 1, K, xput);
+        else
+            sweep<R, 0>(Ls, Lhu, Lhv, Lb, (row + HALO) * C::SX + xseg * R, 1, K, xput);
+    }
+    __syncthreads();
+
+    // ---- y sweep, sources, RK combination, store ------------------------------
     K.a = sc.ay;
     K.hinv_ds = 0.5f * G.inv_dy;
     K.ghinv_ds = -G.g * K.hinv_ds;
