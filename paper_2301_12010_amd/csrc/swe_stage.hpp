@@ -606,19 +606,19 @@ __device__ __forceinline__ void tile_load(const Geo &G, int STAGE, int tx, int t
     using T = TileRegs<C>;
     const int c = threadIdx.x % C::TX, q = threadIdx.x / C::TX;
     if (INNER) {
-        // every pass whose rows lie in the window reads at one per-thread
-        // offset from plane bases advanced by the pass's rows (uniform), so
-        // the loads need no per-load vector arithmetic; rows of a last,
+        // every pass whose rows lie in the window reads the four planes at
+        // one per-thread 32-bit offset (the pass's rows added once), so a
+        // load is the plane's scalar base plus that offset; rows of a last,
         // partial pass are clamped to the window's last row
         const unsigned off = (unsigned)((y0 - HALO + q) * pitch + x0 - HALO + c);
 #pragma unroll
         for (int k = 0; k < T::MI; ++k) {
             if ((k + 1) * T::RPI <= C::WY) {
-                const size_t adv = (size_t)(k * T::RPI) * (size_t)pitch;
-                v.h[k] = pld(w0 + adv, off);
-                v.hu[k] = pld(w1 + adv, off);
-                v.hv[k] = pld(w2 + adv, off);
-                v.b[k] = pld(G.b + adv, off);
+                const unsigned ok = off + (unsigned)(k * T::RPI * pitch);
+                v.h[k] = pld(w0, ok);
+                v.hu[k] = pld(w1, ok);
+                v.hv[k] = pld(w2, ok);
+                v.b[k] = pld(G.b, ok);
             } else {
                 const int r = q + k * T::RPI < C::WY ? q + k * T::RPI : C::WY - 1;
                 const unsigned i = (unsigned)((y0 - HALO + r) * pitch + x0 - HALO + c);
