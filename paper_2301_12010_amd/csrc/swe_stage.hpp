@@ -118,13 +118,19 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
 // 2^30 elements (checked at creation), so the byte offset fits 32 bits and the
 // access takes the scalar-base + 32-bit vector-offset form: one offset
 // register serves every plane, with no 64-bit address arithmetic per plane.
+// The access is declared global: for a Geo read from a table (the batched
+// kernels) the compiler cannot infer where its plane pointers point and
+// would emit flat accesses, which count on the same wait counter as LDS
+// reads, so every LDS wait of the sweeps would also wait for HBM loads.
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) char gchar;
 __device__ __forceinline__ float pld(const float *p, unsigned i)
 {
-    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(p) + (size_t)(i << 2));
+    return *(const gfloat *)((const gchar *)p + (size_t)(i << 2));
 }
 __device__ __forceinline__ void pst(float *p, unsigned i, float v)
 {
-    *reinterpret_cast<float *>(reinterpret_cast<char *>(p) + (size_t)(i << 2)) = v;
+    *(gfloat *)((gchar *)p + (size_t)(i << 2)) = v;
 }
 
 template <int TX_, int TY_, int R_>
@@ -718,10 +724,10 @@ __device__ __forceinline__ void tile_store(const Geo &G, int tx, int ty, const T
             const int layer = !inx ? (gx < 0 ? -1 - gx : gx - nx) : (gy < 0 ? -1 - gy : gy - ny);
             if (G.bc[side] == BC_FIXED && layer < HALO) {
                 const int pos = side < 2 ? gy : gx;
-                h = G.ghost[ghost_index(G, side, 0, layer, pos)];
-                hu = G.ghost[ghost_index(G, side, 1, layer, pos)];
-                hv = G.ghost[ghost_index(G, side, 2, layer, pos)];
-                b = G.ghost[ghost_index(G, side, 3, layer, pos)];
+                h = pld(G.ghost, (unsigned)ghost_index(G, side, 0, layer, pos));
+                hu = pld(G.ghost, (unsigned)ghost_index(G, side, 1, layer, pos));
+                hv = pld(G.ghost, (unsigned)ghost_index(G, side, 2, layer, pos));
+                b = pld(G.ghost, (unsigned)ghost_index(G, side, 3, layer, pos));
             }
         }
         const int li = r * C::SX + cc;
