@@ -28,6 +28,18 @@ __device__ __forceinline__ int upper_index(const T *a, int n, T v)
     return lo;
 }
 
+// Table entries read as kernel arguments are: through the constant address
+// space (the tables do not change during a launch), so a block's (uniform)
+// entry is read with scalar loads into scalar registers.  The Geo stays a
+// reference into the table (a local copy would be spilled to scratch: the
+// ghost code indexes its arrays per lane).
+template <class T>
+__device__ __forceinline__ const T &table_entry(const T *base, int i)
+{
+    return *(const T *)reinterpret_cast<const __attribute__((address_space(4))) T *>(
+        reinterpret_cast<uintptr_t>(base + i));
+}
+
 struct BatchTables {
     const Geo *geo;            // per scenario (batch order)
     const int2 *blk;           // per tile of round 0: (scenario index, tile of that scenario)
@@ -79,7 +91,8 @@ __global__ __launch_bounds__(C::NT, W) void k_persistent(BatchTables T)
                 while (l >= T.prefix[slot + 1]) ++slot;
                 const int tl = l - T.prefix[slot];
                 const int ntx = T.ntx[slot];
-                stage_tile<C, (W <= 2), CMP, IMP, LLF>(T.geo[T.order[slot]], tl % ntx, tl / ntx, lds, r % 3 + 1);
+                const int sc = __builtin_amdgcn_readfirstlane(T.order[slot]);
+                stage_tile<C, (W <= 2), CMP, IMP, LLF>(table_entry(T.geo, sc), tl % ntx, tl / ntx, lds, r % 3 + 1);
                 __syncthreads();
             }
             // every wave makes its own stores visible at agent scope before
@@ -109,10 +122,11 @@ __global__ __launch_bounds__(C::NT, W) void k_round(BatchTables T, int nact_roun
     // scenario and tile, with no search over the prefix sums
     (void)nact_round;
     const int id = xcd_remap_b(blockIdx.x, nblocks);
-    const int2 e = T.blk[id];
-    const Geo &G = T.geo[e.x];
+    const int2 e = table_entry(T.blk, id);
+    const int sc = __builtin_amdgcn_readfirstlane(e.x), tile = __builtin_amdgcn_readfirstlane(e.y);
+    const Geo &G = table_entry(T.geo, sc);
     const int ntx = (G.nx + C::TX - 1) / C::TX;
-    stage_tile<C, (W <= 2), CMP, IMP, LLF>(G, e.y % ntx, e.y / ntx, lds, S);
+    stage_tile<C, (W <= 2), CMP, IMP, LLF>(G, tile % ntx, tile / ntx, lds, S);
 }
 
 struct BatchKernels {
