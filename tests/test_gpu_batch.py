@@ -35,6 +35,8 @@ def small_mix():
         (inputs.dam_break(nx=200, ny=100), 7),
         (inputs.random_wet(20, 20, seed=4), 0),
         (inputs.parabolic_bowl(nx=150, ny=9, dx=4.0), 11),
+        # FIXED west and east sides: the frozen-ghost reads of edge tiles
+        (inputs.steady_slope(perturb=0.05), 6),
     ]
 
 
