@@ -356,35 +356,44 @@ __device__ __forceinline__ void sweep(const float *__restrict__ Ls, const float 
     }
 }
 
-// WENO5-JS of one five-value stencil v (doubled split values, read in the
-// upwind direction; the face lies between v[2] and v[3]): the unnormalised
-// weights a0..a2 (indicators carried 16-fold as in sweep()) and the
-// numerator sum a_k q_k; the reconstruction is num / (a0 + a1 + a2).
+// The three candidate stencils of a five-value stencil v (read in the upwind
+// direction; the face lies between v[2] and v[3]), in the centre form of
+// sweep(): the stencils are centred on v[1], v[2], v[3]; D and E are each
+// centre's second and central differences, and q the candidates' values at
+// the face, t + D + 3E/4, t + E/4 and t - E/4 with t = v_c + D/12.
+__device__ __forceinline__ void weno5_cands(const float v[5], float D[3], float E[3], float q[3])
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        D[k] = fmaf(-2.f, v[k + 1], v[k] + v[k + 2]);
+        E[k] = v[k + 2] - v[k];
+    }
+    q[0] = fmaf(E[0], 0.75f, fmaf(D[0], 1.f / 12.f, v[1]) + D[0]);
+    q[1] = fmaf(E[1], 0.25f, fmaf(D[1], 1.f / 12.f, v[2]));
+    q[2] = fmaf(E[2], -0.25f, fmaf(D[2], 1.f / 12.f, v[3]));
+}
+
+// WENO5-JS of one five-value stencil v (doubled split values): the
+// unnormalised weights a0..a2 (indicators carried 16-fold as in sweep(),
+// from the same centre differences) and the numerator sum a_k q_k; the
+// reconstruction is num / (a0 + a1 + a2).
 __device__ __forceinline__ void weno5_face(const float v[5], const SweepK &K, float &num, float a[3])
 {
-    const float d0 = fmaf(-2.f, v[1], v[0] + v[2]);
-    const float d1 = fmaf(-2.f, v[2], v[1] + v[3]);
-    const float d2 = fmaf(-2.f, v[3], v[2] + v[4]);
-    const float s0 = fmaf(3.f, v[2], fmaf(-4.f, v[1], v[0]));
-    const float s1 = v[1] - v[3];
-    const float s2 = fmaf(3.f, v[2], fmaf(-4.f, v[3], v[4]));
-    a[0] = wt(fmaf(s0, s0, ((13.f / 3.f) * d0) * d0), KD0, K.e0);
-    a[1] = wt(fmaf(s1, s1, ((13.f / 3.f) * d1) * d1), KD1, K.e1);
-    a[2] = wt(fmaf(s2, s2, ((13.f / 3.f) * d2) * d2), KD2, K.e2);
-    // candidate polynomials at the face
-    const float q0 = fmaf(11.f, v[2], fmaf(-7.f, v[1], 2.f * v[0])) * (1.f / 6.f);
-    const float q1 = fmaf(2.f, v[3], fmaf(5.f, v[2], -v[1])) * (1.f / 6.f);
-    const float q2 = fmaf(-1.f, v[4], fmaf(5.f, v[3], 2.f * v[2])) * (1.f / 6.f);
-    num = fmaf(a[2], q2, fmaf(a[1], q1, a[0] * q0));
+    float D[3], E[3], q[3];
+    weno5_cands(v, D, E, q);
+    const float sR = fmaf(2.f, D[0], E[0]), sL = fmaf(2.f, D[2], -E[2]);
+    a[0] = wt(fmaf(sR, sR, ((13.f / 3.f) * D[0]) * D[0]), KD0, K.e0);
+    a[1] = wt(fmaf(E[1], E[1], ((13.f / 3.f) * D[1]) * D[1]), KD1, K.e1);
+    a[2] = wt(fmaf(sL, sL, ((13.f / 3.f) * D[2]) * D[2]), KD2, K.e2);
+    num = fmaf(a[2], q[2], fmaf(a[1], q[1], a[0] * q[0]));
 }
 
 // The same candidates of a stencil of b, combined with given weights.
 __device__ __forceinline__ float weno5_with(const float v[5], const float a[3])
 {
-    const float q0 = fmaf(11.f, v[2], fmaf(-7.f, v[1], 2.f * v[0])) * (1.f / 6.f);
-    const float q1 = fmaf(2.f, v[3], fmaf(5.f, v[2], -v[1])) * (1.f / 6.f);
-    const float q2 = fmaf(-1.f, v[4], fmaf(5.f, v[3], 2.f * v[2])) * (1.f / 6.f);
-    return fmaf(a[2], q2, fmaf(a[1], q1, a[0] * q0));
+    float D[3], E[3], q[3];
+    weno5_cands(v, D, E, q);
+    return fmaf(a[2], q[2], fmaf(a[1], q[1], a[0] * q[0]));
 }
 
 // One sweep with local Lax-Friedrichs splitting (an option; the paper splits
