@@ -133,7 +133,7 @@ void swe_destroy(swe_ctx *ctx);
  * so that increments below half an ulp of the level are kept; removes the
  * FP32 mass drift of shallow wet/dry runs (up to 6e-10 of the mass per step
  * otherwise; about 1e-13 with it).  Costs 8-12 more bytes of traffic per
- * cell and stage and about 20% more time per step.  0 (default): off.  Can
+ * cell and stage and about 4% more time per step.  0 (default): off.  Can
  * be switched at any time (the residual then starts at zero; the captured
  * graph is dropped).  Returns SWE_EINVAL for other values, SWE_ENOMEM when
  * the planes cannot be allocated (the option is then off).  Batches take it

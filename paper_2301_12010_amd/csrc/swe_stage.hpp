@@ -792,11 +792,13 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
     // y-sweep thread -> (column, segment of R cells)
     const int col = tid % TX, seg = tid / TX;
     const int gx = x0 + col;
-    // the per-cell global reads of the combination in the y sweep (g n^2, and
-    // u^n in stages 2 and 3) are issued before the x sweep, so their HBM
-    // latency hides behind both sweeps; indices are clamped into the grid
-    // (cells outside it are skipped)
-    float pgn2[R], pun[R][3];
+    // the per-cell global reads of the combination in the y sweep (g n^2,
+    // u^n in stages 2 and 3, and with the compensated level the residuals of
+    // the input's level and of u^n's) are issued before the x sweep, so
+    // their HBM latency hides behind both sweeps; indices are clamped into
+    // the grid (cells outside it are skipped)
+    float pgn2[R], pun[R][3], prin[R], prun[R];
+    const float *rin = CMP ? (STAGE == 1 ? G.Rl[0] : STAGE == 2 ? G.Rl[1] : G.Rl[2]) : nullptr;
     if (PF) {
         const int cx = gx < nx ? gx : nx - 1;
 #pragma unroll
@@ -808,6 +810,10 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
                 pun[k][0] = pld(G.U[0], gi);
                 pun[k][1] = pld(G.U[1], gi);
                 pun[k][2] = pld(G.U[2], gi);
+            }
+            if (CMP) {
+                prin[k] = pld(rin, gi);
+                if (STAGE != 1) prun[k] = pld(G.Rl[0], gi);
             }
         }
     }
@@ -893,13 +899,13 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
         } else {
             // the same combination on (s, r) pairs with error-free sums and
             // products; the value s + r is carried to ~2^-46 relative
-            const float slo = pld(STAGE == 1 ? G.Rl[0] : STAGE == 2 ? G.Rl[1] : G.Rl[2], gi);
+            const float slo = PF ? prin[k] : pld(rin, gi);
             float yh, yl;
             two_sum(sv, fmaf(dt, Lh_, slo), yh, yl);
             os = yh;
             osl = yl;
             if (STAGE == 2) {
-                const float uh = PF ? pun[k][0] : pld(G.U[0], gi), ul = pld(G.Rl[0], gi);
+                const float uh = PF ? pun[k][0] : pld(G.U[0], gi), ul = PF ? prun[k] : pld(G.Rl[0], gi);
                 const float p1 = 0.75f * uh, e1 = fmaf(0.75f, uh, -p1);
                 float s2, e2;
                 two_sum(p1, 0.25f * yh, s2, e2);
@@ -910,7 +916,7 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
                 ohv = fmaf(0.75f, PF ? pun[k][2] : pld(G.U[2], gi), 0.25f * ohv);
             }
             if (STAGE == 3) {
-                const float uh = PF ? pun[k][0] : pld(G.U[0], gi), ul = pld(G.Rl[0], gi);
+                const float uh = PF ? pun[k][0] : pld(G.U[0], gi), ul = PF ? prun[k] : pld(G.Rl[0], gi);
                 const float un1 = PF ? pun[k][1] : pld(G.U[1], gi);
                 const float un2 = PF ? pun[k][2] : pld(G.U[2], gi);
                 float dh, dl;
