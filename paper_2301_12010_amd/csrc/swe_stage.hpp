@@ -793,11 +793,13 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
     const int col = tid % TX, seg = tid / TX;
     const int gx = x0 + col;
     // the per-cell global reads of the combination in the y sweep (g n^2,
-    // u^n in stages 2 and 3, and with the compensated level the residuals of
-    // the input's level and of u^n's) are issued before the x sweep, so
-    // their HBM latency hides behind both sweeps; indices are clamped into
-    // the grid (cells outside it are skipped)
-    float pgn2[R], pun[R][3], prin[R], prun[R];
+    // u^n in stages 2 and 3, with the compensated level the residuals of the
+    // input's level and of u^n's, and in stage 3 the maximum-depth map when
+    // one is kept) are issued before the x sweep, so their HBM latency hides
+    // behind both sweeps; indices are clamped into the grid (cells outside
+    // it are skipped)
+    const bool track_max = STAGE == 3 && G.hmax != nullptr;
+    float pgn2[R], pun[R][3], prin[R], prun[R], phm[R];
     const float *rin = CMP ? (STAGE == 1 ? G.Rl[0] : STAGE == 2 ? G.Rl[1] : G.Rl[2]) : nullptr;
     if (PF) {
         const int cx = gx < nx ? gx : nx - 1;
@@ -815,6 +817,7 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
                 prin[k] = pld(rin, gi);
                 if (STAGE != 1) prun[k] = pld(G.Rl[0], gi);
             }
+            if (track_max) phm[k] = pld(G.hmax, gi);
         }
     }
 
@@ -954,9 +957,9 @@ __device__ __forceinline__ void tile_compute(const Geo &G, const StageScalars &s
         pst(O[0], gi, os);
         pst(O[1], gi, ohu);
         pst(O[2], gi, ohv);
-        if (STAGE == 3 && G.hmax) {
+        if (track_max) {
             // maximum-depth map over the states after completed steps
-            if (oh > pld(G.hmax, gi)) pst(G.hmax, gi, oh);
+            if (oh > (PF ? phm[k] : pld(G.hmax, gi))) pst(G.hmax, gi, oh);
         }
         // wave speeds of the output (the next stage's input), as float bits:
         // a speed is +0 or more, so its bits order as unsigned integers, and a
