@@ -92,7 +92,10 @@ __global__ __launch_bounds__(C::NT, W) void k_persistent(BatchTables T)
                 const int tl = l - T.prefix[slot];
                 const int ntx = T.ntx[slot];
                 const int sc = __builtin_amdgcn_readfirstlane(T.order[slot]);
-                stage_tile<C, (W <= 2), CMP, IMP, LLF>(table_entry(T.geo, sc), tl % ntx, tl / ntx, lds, r % 3 + 1);
+                // no early per-cell reads with the compensated level: with the
+                // ticket loop's registers they would spill on some tiles
+                stage_tile<C, (W <= 2) && !CMP, CMP, IMP, LLF>(table_entry(T.geo, sc), tl % ntx, tl / ntx, lds,
+                                                               r % 3 + 1);
                 __syncthreads();
             }
             // every wave makes its own stores visible at agent scope before
