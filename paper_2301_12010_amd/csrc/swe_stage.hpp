@@ -10,7 +10,9 @@
 //   1. the tile's input state (s, hu, hv, b) with a 3-cell halo is staged in
 //      LDS in coalesced row passes (s is the stored level, see Geo); ghosts
 //      are mirrored or read from frozen planes on the fly, so no separate
-//      ghost pass exists;
+//      ghost pass exists.  The per-cell global reads that step 3 combines
+//      (g n^2, u^n, residuals, the maximum-depth map) are issued next, so
+//      their latency hides behind both sweeps;
 //   2. x sweep: each thread walks R consecutive cells of one row, keeping a
 //      3-cell window of split fluxes in registers.  Every cell centre's
 //      second and first differences, the three smoothness indicators and the
